@@ -1,0 +1,198 @@
+/*
+ * hlb.h -- C ABI of libhlb: bit-exact ciphertext-plaintext matrix products (CP-MM) for CKKS
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the reduction of CP-MM to modular plaintext matrix products
+ * (Mod-PP-MM) over each RNS prime (Algorithm alg:pcmm step 1; Theorems th:pcmm and
+ * th:pcmm-shs), and evaluates every Mod-PP-MM exactly as matrix products of small limbs
+ * followed by an integer recombination and a reduction modulo q (Section 6.1, Strategy 1,
+ * Lemma le:strategy1 and Eq decomp).  Two limb forms are provided:
+ *   HLB_FORM_INT8  balanced signed 8-bit digits multiplied on the INT8->INT32 matrix cores,
+ *   HLB_FORM_FP64  17..26-bit limbs multiplied on the FP64 matrix cores (the paper's form).
+ * Both produce the unique canonical result in [0, q) -- bit-identical to each other.
+ *
+ * Orientation.  The paper multiplies an encrypted matrix on the right, M * U.  This ABI takes
+ * the plaintext on the LEFT, C = P * X, which is the same computation on transposed
+ * matrices; a ciphertext (A, B) satisfying the row identity A * S + B = Delta * M (mod q)
+ * (Eq mat_row_format) is mapped by left multiplication to (P A, P B), an encryption of P M.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are row-major.  "ld" arguments are row strides in ELEMENTS (>= row length).
+ *  - Matrix pointers are DEVICE pointers owned by the caller; the library never frees them.
+ *    Prime lists, problem tables and result scalars are HOST pointers.
+ *  - Residues are uint64 values in [0, q).  Plaintext matrices are signed int64.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Product calls only
+ *    enqueue work on it and return; results are ready when the stream is synchronised.
+ *    Argument and planning errors are reported synchronously, before anything is enqueued.
+ *    Entry points documented as "synchronous" synchronise `stream` before returning.
+ *  - Moduli: 2 <= q < 2^52.
+ *  - Workspace (digit planes for the INT8 form) is allocated by the library from a
+ *    stream-ordered pool and freed in stream order; hlb_release() returns pooled memory.
+ *  - Calls on different streams may run concurrently.
+ *  - The functions are not re-entrant during hlb_release().
+ */
+#ifndef HLB_H
+#define HLB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HLB_OK = 0,
+    HLB_EINVAL = 1,  /* bad shape, null pointer, leading dimension, count or modulus */
+    HLB_ERANGE = 2,  /* an input entry lies outside its stated range (checked entry points) */
+    HLB_EBOUND = 3,  /* no exact limb plan exists for this form, shape and input bound */
+    HLB_ENOMEM = 4,  /* device workspace allocation failed */
+    HLB_EDEVICE = 5, /* a HIP runtime call or kernel launch failed */
+    HLB_EUNSUP = 6   /* device is not gfx950, or the requested option is unknown */
+} hlb_status;
+
+typedef enum {
+    HLB_FORM_AUTO = 0, /* INT8 where a plan exists, else FP64 */
+    HLB_FORM_FP64 = 1, /* FP64 limbs on v_mfma_f64_16x16x4_f64 */
+    HLB_FORM_INT8 = 2  /* balanced int8 digits on v_mfma_i32_32x32x32_i8 */
+} hlb_form;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *hlb_status_str(int status);
+
+/*
+ * Mod-PP-MM_{q; m,k,n} (Section 5 notation): C = P * X mod q.
+ *   P: m x k residues in [0, q) (row stride ldp >= k), X: k x n residues (ldx >= n),
+ *   C: m x n output, written with canonical residues in [0, q) (ldc >= n).
+ * m == 0 or n == 0 is a no-op; k == 0 writes zeros.  Inputs >= q violate the precondition
+ * (the result is then unspecified but the call stays memory-safe); check them with
+ * hlb_validate_residues.  C must not alias P or X.
+ */
+hlb_status hlb_mod_pp_mm(uint64_t q, int64_t m, int64_t k, int64_t n,
+                         const uint64_t *P, int64_t ldp, const uint64_t *X, int64_t ldx,
+                         uint64_t *C, int64_t ldc, int form, void *stream);
+
+/*
+ * CP-MM over L RNS primes (Algorithm alg:pcmm step 1 without the Rescale; Theorem
+ * th:pcmm-shs: two Mod-PP-MMs per modulus):
+ *     PA[l] = P * A[l] mod primes[l],   PB[l] = P * B[l] mod primes[l],   l < L.
+ *   P:  m x k signed plaintext (ldp >= k) with every |P[i][j]| <= p_absmax.
+ *       The same P serves all primes and both parts: it is split into digits once.
+ *   p_absmax: a bound on |P| (1 <= p_absmax < 2^52).  Pass 0 to have the library measure
+ *       it on the device (that makes the call synchronous).
+ *   A:  [L][k][nA] residues, dense (prime l's matrix at A + l*k*nA); B: [L][k][nB].
+ *   PA: [L][m][nA] output, dense; PB: [L][m][nB] output, dense.
+ *   primes: host array of L moduli, each 2 <= q < 2^52.
+ * L == 0, m == 0 or nA == nB == 0 are no-ops.  |P| > p_absmax violates the precondition.
+ */
+hlb_status hlb_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB,
+                     const int64_t *P, int64_t ldp, int64_t p_absmax,
+                     const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L,
+                     uint64_t *PA, uint64_t *PB, int form, void *stream);
+
+/* One CP-MM of a batch: the fields mean what the hlb_cp_mm arguments of the same names
+ * mean (dense layouts [L][k][nA], [L][k][nB], [L][m][nA], [L][m][nB]; P row stride ldp). */
+typedef struct {
+    int64_t m, k, nA, nB;
+    const int64_t *P;
+    int64_t ldp;
+    int64_t p_absmax;
+    const uint64_t *A, *B;
+    uint64_t *PA, *PB;
+} hlb_cpmm_problem;
+
+/*
+ * A batch of independent CP-MMs of uneven shapes that share the L primes (Theorem
+ * th:pcmm-shs applied to each problem; the per-prime products are independent, as in
+ * Section 6.1 Strategy 3).  All products run in ONE persistent kernel launch that pulls
+ * output tiles from a work list (largest first), preceded by one digit-split launch for all
+ * plaintexts and one for all ciphertext parts; the launch sequence is captured once per
+ * distinct batch signature (shapes, pointers, primes) into a HIP graph and replayed.
+ *   probs: host array of `count` problems (count >= 0).  Output buffers must not overlap.
+ * Results are bit-identical to calling hlb_cp_mm on each problem.
+ */
+hlb_status hlb_cp_mm_batch(const hlb_cpmm_problem *probs, int count, const uint64_t *primes,
+                           int L, int form, void *stream);
+
+/*
+ * Synchronous check that every entry of a rows x cols residue matrix (row stride ld) is
+ * < q.  *first_bad (host) receives the row-major linear index (row*cols + col) of the first
+ * offending entry, or -1.  Returns HLB_ERANGE if one exists, HLB_OK otherwise.
+ */
+hlb_status hlb_validate_residues(const uint64_t *X, int64_t rows, int64_t cols, int64_t ld,
+                                 uint64_t q, int64_t *first_bad, void *stream);
+
+/* Synchronous: *absmax (host) = max |P[i][j]| over an m x k signed matrix (row stride ld);
+ * values equal to INT64_MIN report INT64_MAX. */
+hlb_status hlb_plaintext_absmax(const int64_t *P, int64_t m, int64_t k, int64_t ld,
+                                int64_t *absmax, void *stream);
+
+/*
+ * Limb plan the library would use (host only, no device work).  Exactness rule (Lemma
+ * le:strategy1): every partial sum of limb products must stay below 2^31 in magnitude
+ * (INT8 form, int32 accumulators) or 2^53 (FP64 form), so the plan fixes the limb counts
+ * and the number of K steps accumulated before a fold into a 64-bit residue.
+ *   kind: 0 = Mod-PP-MM (P is a residue < q), 1 = CP-MM (|P| <= p_absmax).
+ */
+typedef struct {
+    int form;          /* HLB_FORM_INT8 or HLB_FORM_FP64 */
+    int p_limbs;       /* limbs (digits) of the left operand */
+    int x_limbs;       /* limbs (digits) of the right operand */
+    int shifts;        /* accumulators per output = p_limbs + x_limbs - 1 */
+    int limb_bits;     /* bits per limb: 8 (INT8) or w (FP64) */
+    int max_pairs;     /* largest number of limb products sharing one accumulator */
+    int64_t k_chunk;   /* K elements accumulated before a fold (>= k means no fold) */
+    double acc_bound_log2; /* log2 of the bound on |accumulator| used to size k_chunk */
+} hlb_plan_desc;
+
+hlb_status hlb_plan(int kind, int64_t k, uint64_t q_max, int64_t p_absmax, int form,
+                    hlb_plan_desc *out);
+
+/* Library options (process-wide).  Mainly for tests and measurement. */
+typedef enum {
+    HLB_OPT_FORCE_KCHUNK = 1, /* >0: cap the fold chunk at this many K elements (rounded to
+                                 the kernel's K step); 0 restores the planned chunk */
+    HLB_OPT_PROFILE = 2,      /* 1: bracket every kernel launch with HIP events */
+    HLB_OPT_BATCH_GRAPH = 3   /* 1 (default): capture/replay batches as HIP graphs; 0: eager */
+} hlb_option;
+
+hlb_status hlb_set_option(int option, int64_t value);
+
+/*
+ * Kernel timing collected while HLB_OPT_PROFILE is on (synchronous: waits for the
+ * recorded events).  For kernel class `name` ("gemm_i8", "gemm_f64", "split_p",
+ * "split_x", "batch_i8"), *launches receives the number of launches and *total_ms their
+ * summed durations measured between events recorded on each launch's stream.  Unknown
+ * names report zero.  Collected records are cleared by hlb_profile_reset().
+ */
+hlb_status hlb_profile_read(const char *name, int64_t *launches, double *total_ms);
+hlb_status hlb_profile_reset(void);
+
+/* Frees pooled workspace and cached batch graphs (synchronises the device). */
+hlb_status hlb_release(void);
+
+/* ------------------------------------------------------------------------------------ */
+/* Test-only helpers (not part of the product contract): CKKS coefficient encoding and a  */
+/* matrix-form encryption/decryption, written from Section 2.2 and Eq mat_row_format.     */
+/* ------------------------------------------------------------------------------------ */
+
+/* out[i] = floor(delta * M[i] + 1/2) for `count` doubles (the paper's rounding). */
+hlb_status hlb_test_encode(const double *M, int64_t count, double delta, int64_t *out,
+                           void *stream);
+
+/* B[l] = -(A[l] * S) + Menc (mod primes[l]) for l < L, where A: [L][k][n] residues,
+ * S: n x n signed (int64, small), Menc: k x n signed (the encoded message plus error),
+ * B: [L][k][n] output. */
+hlb_status hlb_test_encrypt(int64_t k, int64_t n, const uint64_t *A, const int64_t *S,
+                            const int64_t *Menc, const uint64_t *primes, int L, uint64_t *B,
+                            void *stream);
+
+/* D[l] = A[l] * S + B[l] (mod primes[l]); A, B: [L][rows][n], S: n x n signed, D output. */
+hlb_status hlb_test_decrypt(int64_t rows, int64_t n, const uint64_t *A, const uint64_t *B,
+                            const int64_t *S, const uint64_t *primes, int L, uint64_t *D,
+                            void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HLB_H */

@@ -1,0 +1,600 @@
+// api.cpp -- libhlb host side: argument checks, the exact limb planner, workspace, kernel
+// dispatch and the extern "C" entry points declared in include/hlb.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hlb.h"
+#include "common.hpp"
+#include "launch.hpp"
+#include "host.hpp"
+
+namespace hlb {
+
+// ---------------------------------------------------------------------------------------
+// Options and profiling
+// ---------------------------------------------------------------------------------------
+static std::atomic<int64_t> g_force_kchunk{0};
+static std::atomic<int> g_profile{0};
+static std::atomic<int> g_batch_graph{1};
+
+int64_t opt_force_kchunk() { return g_force_kchunk.load(); }
+bool opt_batch_graph() { return g_batch_graph.load() != 0; }
+
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static std::vector<ProfRec> g_prof;
+
+ProfScope::ProfScope(const char *name, hipStream_t s) : stream_(s) {
+    if (!g_profile.load()) return;
+    name_ = name;
+    if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) return;
+    if (hipEventRecord(a_, s) != hipSuccess) return;
+    active_ = true;
+}
+ProfScope::~ProfScope() {
+    if (!active_) return;
+    if (hipEventRecord(b_, stream_) != hipSuccess) return;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof.push_back({name_, a_, b_});
+}
+
+// ---------------------------------------------------------------------------------------
+// Device checks
+// ---------------------------------------------------------------------------------------
+struct DevInfo {
+    int checked = 0;
+    bool ok = false;
+    int n_xcd = 8;
+    bool pool_set = false;
+};
+static std::mutex g_dev_mu;
+static DevInfo g_dev[64];
+
+hlb_status device_ready(int *n_xcd) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return HLB_EDEVICE;
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    DevInfo &d = g_dev[dev];
+    if (!d.checked) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess) return HLB_EDEVICE;
+        d.checked = 1;
+        d.ok = std::strncmp(p.gcnArchName, "gfx950", 6) == 0;
+        // gfx950 has 32 CUs per XCD; a partitioned device exposes fewer XCDs
+        d.n_xcd = std::max(1, p.multiProcessorCount / 32);
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;  // keep freed workspace cached in the pool
+            d.pool_set = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr) == hipSuccess;
+        }
+    }
+    if (!d.ok) return HLB_EUNSUP;
+    if (n_xcd) *n_xcd = d.n_xcd;
+    return HLB_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Planner (Lemma le:strategy1's exactness condition, per form)
+// ---------------------------------------------------------------------------------------
+
+// Largest value representable with D balanced int8 digits: 127 * (256^D - 1) / 255.
+static uint64_t i8_capacity(int D) {
+    uint64_t c = 0;
+    for (int j = 0; j < D; ++j) c = c * 256 + 127;
+    return c;
+}
+static int i8_digits(uint64_t vmax) {
+    for (int D = 1; D <= 7; ++D)
+        if (vmax <= i8_capacity(D)) return D;
+    return 8;
+}
+static int bit_length(uint64_t v) {
+    int b = 0;
+    while (v) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+static int64_t cap_chunk(int64_t chunk, int64_t step) {
+    const int64_t f = opt_force_kchunk();
+    if (f > 0 && f < chunk) chunk = f;
+    chunk = chunk / step * step;
+    return chunk;
+}
+
+hlb_status plan_i8(int kind, int64_t k, uint64_t qmax, int64_t pmax, Plan *pl) {
+    const int dx = i8_digits(qmax - 1);
+    const int dp = kind == 0 ? dx : i8_digits((uint64_t)pmax);
+    int ip = 0, ix = 0;
+    if (dp <= 3 && dx <= 6) ip = 3, ix = 6;
+    else if (dp <= 3 && dx == 7) ip = 3, ix = 7;
+    else if (dp <= 7 && dx <= 7) ip = 7, ix = 7;
+    else return HLB_EBOUND;
+    const I8Shape sh = i8_shape(ip, ix);
+    if (!sh.dp) return HLB_EBOUND;
+    const int pairs = std::min(ip, ix);
+    // |c_s| <= pairs * kchunk * 128 * 128 must stay <= 2^31 - 1
+    const int64_t limit = ((int64_t)1 << 31) - 1;
+    const int64_t chunk = cap_chunk(limit / ((int64_t)pairs * 16384), kBK8);
+    if (chunk < kBK8) return HLB_EBOUND;
+    pl->form = HLB_FORM_INT8;
+    pl->np = ip;
+    pl->nx = ix;
+    pl->limb_bits = 8;
+    pl->pairs = pairs;
+    pl->kchunk = chunk;
+    pl->bm = sh.bm;
+    pl->bn = sh.bn;
+    pl->bk = kBK8;
+    pl->acc_bound_log2 = std::log2((double)pairs * (double)std::min<int64_t>(k, chunk) * 16384.0);
+    return HLB_OK;
+}
+
+hlb_status plan_f64(int kind, int64_t k, uint64_t qmax, int64_t pmax, Plan *pl) {
+    const double lim = 9007199254740991.0;  // 2^53 - 1
+    const int xbits = bit_length(qmax - 1);
+    const int64_t kk = std::max<int64_t>(k, 1);
+    if (kind == 1) {
+        // one signed plaintext limb (k2 = 1), X in NX limbs of w bits:
+        // kchunk * pmax * (2^w - 1) < 2^53
+        for (int nx = 3; nx <= 4; ++nx) {
+            const int w = (xbits + nx - 1) / nx;
+            if (w < 1) continue;
+            const double per = (double)std::max<int64_t>(pmax, 1) * (double)(((uint64_t)1 << w) - 1);
+            const int64_t raw = (int64_t)std::min(lim / per, 4.0e18);
+            const int64_t chunk = cap_chunk(raw, kBK64);
+            if (chunk >= kBK64 && (chunk >= kk || nx == 4)) {
+                pl->form = HLB_FORM_FP64;
+                pl->np = 1;
+                pl->nx = nx;
+                pl->limb_bits = w;
+                pl->pairs = 1;
+                pl->kchunk = chunk;
+                pl->bm = 64;
+                pl->bn = 64;
+                pl->bk = kBK64;
+                pl->acc_bound_log2 = std::log2(per * (double)std::min<int64_t>(kk, chunk));
+                return HLB_OK;
+            }
+        }
+    }
+    // both operands in L limbs of w bits (P in sign-magnitude limbs):
+    // L * kchunk * (2^w - 1)^2 < 2^53
+    const int bits = std::max(xbits, kind == 1 ? bit_length((uint64_t)pmax) : xbits);
+    for (int L = 3; L <= 4; ++L) {
+        const int w = (bits + L - 1) / L;
+        const double lm = (double)(((uint64_t)1 << w) - 1);
+        const double per = (double)L * lm * lm;
+        const int64_t raw = (int64_t)std::min(lim / per, 4.0e18);
+        const int64_t chunk = cap_chunk(raw, kBK64);
+        if (chunk >= kBK64 && (chunk >= kk || L == 4)) {
+            pl->form = HLB_FORM_FP64;
+            pl->np = L;
+            pl->nx = L;
+            pl->limb_bits = w;
+            pl->pairs = L;
+            pl->kchunk = chunk;
+            pl->bm = 64;
+            pl->bn = 64;
+            pl->bk = kBK64;
+            pl->acc_bound_log2 = std::log2(per * (double)std::min<int64_t>(kk, chunk));
+            return HLB_OK;
+        }
+    }
+    return HLB_EBOUND;
+}
+
+hlb_status plan(int kind, int64_t k, uint64_t qmax, int64_t pmax, int form, Plan *pl) {
+    if (form == HLB_FORM_INT8) return plan_i8(kind, k, qmax, pmax, pl);
+    if (form == HLB_FORM_FP64) return plan_f64(kind, k, qmax, pmax, pl);
+    if (form == HLB_FORM_AUTO) {
+        if (plan_i8(kind, k, qmax, pmax, pl) == HLB_OK) return HLB_OK;
+        return plan_f64(kind, k, qmax, pmax, pl);
+    }
+    return HLB_EINVAL;
+}
+
+void fill_seg(Seg &s, uint64_t q, int limb_bits) {
+    s.q = q;
+    s.qinv = 1.0 / (double)q;
+    const unsigned __int128 w = ((unsigned __int128)1 << limb_bits) % q;
+    s.wmod = (uint64_t)w;
+    s.wshoup = (uint64_t)((w << 64) / q);
+}
+
+hlb_status check_modulus(uint64_t q) { return (q >= 2 && q < kMaxModulus) ? HLB_OK : HLB_EINVAL; }
+
+// ---------------------------------------------------------------------------------------
+// Workspace: stream-ordered allocations from the device's default pool (kept cached).
+// ---------------------------------------------------------------------------------------
+hlb_status ws_alloc(void **p, size_t bytes, hipStream_t s) {
+    *p = nullptr;
+    if (bytes == 0) return HLB_OK;
+    if (hipMallocAsync(p, bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return HLB_ENOMEM;
+    }
+    return HLB_OK;
+}
+void ws_free(void *p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+// ---------------------------------------------------------------------------------------
+// One GEMM launch over up to kMaxSegs output segments sharing the left operand.
+// ---------------------------------------------------------------------------------------
+struct OutSpec {
+    uint64_t *C;
+    const uint64_t *X;  // right operand (k x n, row stride ldx)
+    int64_t ldc, ldx, n;
+    uint64_t q;
+};
+
+// Runs C_s = P * X_s mod q_s for every segment s (left operand shared): the plaintext split
+// once, the right operands split per segment, then GEMM launches of <= kMaxSegs segments.
+hlb_status run_products(const Plan &pl, const int64_t *P, int64_t ldp, int64_t m, int64_t k,
+                        const std::vector<OutSpec> &outs, int n_xcd, hipStream_t s) {
+    if (m == 0 || outs.empty()) return HLB_OK;
+    if (k == 0) {
+        for (const OutSpec &o : outs)
+            if (o.n > 0 && hipMemset2DAsync(o.C, o.ldc * 8, 0, o.n * 8, m, s) != hipSuccess) return HLB_EDEVICE;
+        return HLB_OK;
+    }
+    const int64_t tiles_m = (m + pl.bm - 1) / pl.bm;
+    const int64_t kblocks = (k + pl.bk - 1) / pl.bk;
+    const int64_t kfold = std::max<int64_t>(1, pl.kchunk / pl.bk);
+    std::vector<int64_t> seg_tiles(outs.size());
+    int64_t tiles_total = 0;
+    for (size_t i = 0; i < outs.size(); ++i) {
+        seg_tiles[i] = (outs[i].n + pl.bn - 1) / pl.bn;
+        tiles_total += seg_tiles[i];
+    }
+    // grid sizes and in-kernel tile indices are 32-bit
+    if (kblocks > INT32_MAX / 2 || tiles_total > INT32_MAX / 2 || tiles_m * tiles_total > INT32_MAX / 2)
+        return HLB_EINVAL;
+
+    void *wsP = nullptr, *wsX = nullptr;
+    const int64_t p_tile = (int64_t)pl.np * pl.bm * kBK8, x_tile = (int64_t)pl.nx * pl.bn * kBK8;
+    if (pl.form == HLB_FORM_INT8) {
+        hlb_status st = ws_alloc(&wsP, (size_t)(tiles_m * kblocks * p_tile), s);
+        if (st != HLB_OK) return st;
+        st = ws_alloc(&wsX, (size_t)(tiles_total * kblocks * x_tile), s);
+        if (st != HLB_OK) {
+            ws_free(wsP, s);
+            return st;
+        }
+        {
+            ProfScope ps("split_p", s);
+            if (launch_split_rows_i8(pl.np, pl.bm, P, ldp, m, k, (int)tiles_m, (int)kblocks, (int8_t *)wsP, s) !=
+                hipSuccess) {
+                ws_free(wsP, s);
+                ws_free(wsX, s);
+                return HLB_EDEVICE;
+            }
+        }
+        int64_t t0 = 0;
+        for (size_t i = 0; i < outs.size(); ++i) {
+            ProfScope ps("split_x", s);
+            int8_t *dst = (int8_t *)wsX + t0 * kblocks * x_tile;
+            if (launch_split_cols_i8(pl.nx, pl.bn, outs[i].X, outs[i].ldx, k, outs[i].n, (int)seg_tiles[i],
+                                     (int)kblocks, dst, s) != hipSuccess) {
+                ws_free(wsP, s);
+                ws_free(wsX, s);
+                return HLB_EDEVICE;
+            }
+            t0 += seg_tiles[i];
+        }
+    }
+
+    hlb_status result = HLB_OK;
+    int64_t tile_base = 0;
+    for (size_t first = 0; first < outs.size(); first += kMaxSegs) {
+        const size_t last = std::min(outs.size(), first + kMaxSegs);
+        GemmArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.Pd = (const int8_t *)wsP;
+        a.Xd = wsX ? (const int8_t *)wsX + tile_base * kblocks * x_tile : nullptr;
+        a.P = P;
+        a.ldp = ldp;
+        a.m = m;
+        a.k = k;
+        a.kblocks = (int)kblocks;
+        a.kfold = kfold >= kblocks ? (int)kblocks + 1 : (int)kfold;  // >= kblocks: no fold
+        a.tiles_m = (int)tiles_m;
+        a.group_m = 4;
+        a.n_xcd = n_xcd;
+        a.limb_bits = pl.limb_bits;
+        int32_t tb = 0;
+        for (size_t i = first; i < last; ++i) {
+            Seg &sg = a.seg[a.nseg++];
+            sg.C = outs[i].C;
+            sg.X = outs[i].X;
+            sg.ldc = outs[i].ldc;
+            sg.ldx = outs[i].ldx;
+            sg.n = outs[i].n;
+            fill_seg(sg, outs[i].q, pl.limb_bits);
+            sg.tile_begin = tb;
+            sg.tiles = (int32_t)seg_tiles[i];
+            tb += sg.tiles;
+        }
+        a.tiles_n = tb;
+        tile_base += tb;
+        if (tb == 0) continue;
+        hipError_t e;
+        if (pl.form == HLB_FORM_INT8) {
+            ProfScope ps("gemm_i8", s);
+            e = launch_gemm_i8(pl.np, pl.nx, a, s);
+        } else {
+            ProfScope ps("gemm_f64", s);
+            e = launch_gemm_f64(pl.np, pl.nx, a, s);
+        }
+        if (e != hipSuccess) {
+            result = HLB_EDEVICE;
+            break;
+        }
+    }
+    ws_free(wsP, s);
+    ws_free(wsX, s);
+    return result;
+}
+
+hlb_status measure_absmax(const int64_t *P, int64_t m, int64_t k, int64_t ld, int64_t *out, hipStream_t s) {
+    unsigned long long *d = nullptr;
+    if (hipMallocAsync((void **)&d, sizeof(*d), s) != hipSuccess) return HLB_ENOMEM;
+    hlb_status st = HLB_OK;
+    if (hipMemsetAsync(d, 0, sizeof(*d), s) != hipSuccess) st = HLB_EDEVICE;
+    if (st == HLB_OK && m > 0 && k > 0 && launch_absmax(P, m, k, ld, d, s) != hipSuccess) st = HLB_EDEVICE;
+    unsigned long long h = 0;
+    if (st == HLB_OK && hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) st = HLB_EDEVICE;
+    (void)hipFreeAsync(d, s);
+    if (hipStreamSynchronize(s) != hipSuccess) st = HLB_EDEVICE;
+    if (st == HLB_OK) *out = h > (unsigned long long)INT64_MAX ? INT64_MAX : (int64_t)h;
+    return st;
+}
+
+}  // namespace hlb
+
+using namespace hlb;
+
+// ===========================================================================================
+// extern "C" entry points
+// ===========================================================================================
+extern "C" {
+
+const char *hlb_status_str(int s) {
+    switch (s) {
+        case HLB_OK: return "ok";
+        case HLB_EINVAL: return "invalid argument";
+        case HLB_ERANGE: return "input entry out of range";
+        case HLB_EBOUND: return "no exact limb plan for this form and shape";
+        case HLB_ENOMEM: return "device workspace allocation failed";
+        case HLB_EDEVICE: return "HIP runtime or kernel launch failure";
+        case HLB_EUNSUP: return "unsupported device or option";
+        default: return "unknown status";
+    }
+}
+
+hlb_status hlb_plan(int kind, int64_t k, uint64_t q_max, int64_t p_absmax, int form, hlb_plan_desc *out) {
+    if (!out || (kind != 0 && kind != 1) || k < 0 || check_modulus(q_max) != HLB_OK) return HLB_EINVAL;
+    if (kind == 1 && (p_absmax < 1 || (uint64_t)p_absmax >= kMaxModulus)) return HLB_EINVAL;
+    Plan pl;
+    const hlb_status st = plan(kind, k, q_max, p_absmax, form, &pl);
+    if (st != HLB_OK) return st;
+    out->form = pl.form;
+    out->p_limbs = pl.np;
+    out->x_limbs = pl.nx;
+    out->shifts = pl.np + pl.nx - 1;
+    out->limb_bits = pl.limb_bits;
+    out->max_pairs = pl.pairs;
+    out->k_chunk = pl.kchunk;
+    out->acc_bound_log2 = pl.acc_bound_log2;
+    return HLB_OK;
+}
+
+hlb_status hlb_mod_pp_mm(uint64_t q, int64_t m, int64_t k, int64_t n, const uint64_t *P, int64_t ldp,
+                         const uint64_t *X, int64_t ldx, uint64_t *C, int64_t ldc, int form, void *stream) {
+    if (check_modulus(q) != HLB_OK || m < 0 || k < 0 || n < 0) return HLB_EINVAL;
+    if (m == 0 || n == 0) return HLB_OK;
+    if (!C || ldc < n || (k > 0 && (!P || !X || ldp < k || ldx < n))) return HLB_EINVAL;
+    Plan pl;
+    hlb_status st = plan(0, k, q, 0, form, &pl);
+    if (st != HLB_OK) return st;
+    int n_xcd = 8;
+    if ((st = device_ready(&n_xcd)) != HLB_OK) return st;
+    std::vector<OutSpec> outs{{C, X, ldc, ldx, n, q}};
+    return run_products(pl, (const int64_t *)P, ldp, m, k, outs, n_xcd, (hipStream_t)stream);
+}
+
+hlb_status hlb_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp,
+                     int64_t p_absmax, const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L,
+                     uint64_t *PA, uint64_t *PB, int form, void *stream) {
+    if (m < 0 || k < 0 || nA < 0 || nB < 0 || L < 0 || L > 1024 || p_absmax < 0 ||
+        (uint64_t)p_absmax >= kMaxModulus)
+        return HLB_EINVAL;
+    if (L == 0 || m == 0 || (nA == 0 && nB == 0)) return HLB_OK;
+    if (!primes) return HLB_EINVAL;
+    uint64_t qmax = 0;
+    for (int l = 0; l < L; ++l) {
+        if (check_modulus(primes[l]) != HLB_OK) return HLB_EINVAL;
+        qmax = std::max(qmax, primes[l]);
+    }
+    if ((nA > 0 && !PA) || (nB > 0 && !PB)) return HLB_EINVAL;
+    if (k > 0 && (!P || ldp < k || (nA > 0 && !A) || (nB > 0 && !B))) return HLB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int n_xcd = 8;
+    hlb_status st = device_ready(&n_xcd);
+    if (st != HLB_OK) return st;
+    if (p_absmax == 0 && k > 0) {
+        if ((st = measure_absmax(P, m, k, ldp, &p_absmax, s)) != HLB_OK) return st;
+        if ((uint64_t)p_absmax >= kMaxModulus) return HLB_ERANGE;
+    }
+    Plan pl;
+    if ((st = plan(1, k, qmax, std::max<int64_t>(p_absmax, 1), form, &pl)) != HLB_OK) return st;
+    std::vector<OutSpec> outs;
+    for (int l = 0; l < L; ++l) {
+        if (nA > 0) outs.push_back({PA + (int64_t)l * m * nA, A + (int64_t)l * k * nA, nA, nA, nA, primes[l]});
+        if (nB > 0) outs.push_back({PB + (int64_t)l * m * nB, B + (int64_t)l * k * nB, nB, nB, nB, primes[l]});
+    }
+    return run_products(pl, P, ldp, m, k, outs, n_xcd, s);
+}
+
+hlb_status hlb_validate_residues(const uint64_t *X, int64_t rows, int64_t cols, int64_t ld, uint64_t q,
+                                 int64_t *first_bad, void *stream) {
+    if (!first_bad || rows < 0 || cols < 0 || q < 1) return HLB_EINVAL;
+    *first_bad = -1;
+    if (rows == 0 || cols == 0) return HLB_OK;
+    if (!X || ld < cols) return HLB_EINVAL;
+    hlb_status st = device_ready(nullptr);
+    if (st != HLB_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *d = nullptr;
+    if (hipMallocAsync((void **)&d, sizeof(*d), s) != hipSuccess) return HLB_ENOMEM;
+    unsigned long long h = ~0ull;
+    if (hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s) != hipSuccess) st = HLB_EDEVICE;
+    if (st == HLB_OK && launch_validate(X, rows, cols, ld, q, d, s) != hipSuccess) st = HLB_EDEVICE;
+    if (st == HLB_OK && hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) st = HLB_EDEVICE;
+    (void)hipFreeAsync(d, s);
+    if (hipStreamSynchronize(s) != hipSuccess) st = HLB_EDEVICE;
+    if (st != HLB_OK) return st;
+    if (h != ~0ull) {
+        *first_bad = (int64_t)h;
+        return HLB_ERANGE;
+    }
+    return HLB_OK;
+}
+
+hlb_status hlb_plaintext_absmax(const int64_t *P, int64_t m, int64_t k, int64_t ld, int64_t *absmax,
+                                void *stream) {
+    if (!absmax || m < 0 || k < 0) return HLB_EINVAL;
+    *absmax = 0;
+    if (m == 0 || k == 0) return HLB_OK;
+    if (!P || ld < k) return HLB_EINVAL;
+    hlb_status st = device_ready(nullptr);
+    if (st != HLB_OK) return st;
+    return measure_absmax(P, m, k, ld, absmax, (hipStream_t)stream);
+}
+
+hlb_status hlb_set_option(int option, int64_t value) {
+    switch (option) {
+        case HLB_OPT_FORCE_KCHUNK:
+            if (value < 0) return HLB_EINVAL;
+            g_force_kchunk.store(value);
+            return HLB_OK;
+        case HLB_OPT_PROFILE:
+            g_profile.store(value ? 1 : 0);
+            return HLB_OK;
+        case HLB_OPT_BATCH_GRAPH:
+            g_batch_graph.store(value ? 1 : 0);
+            return HLB_OK;
+        default: return HLB_EUNSUP;
+    }
+}
+
+hlb_status hlb_profile_read(const char *name, int64_t *launches, double *total_ms) {
+    if (!name || !launches || !total_ms) return HLB_EINVAL;
+    *launches = 0;
+    *total_ms = 0.0;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (ProfRec &r : g_prof) {
+        if (r.name != name) continue;
+        if (hipEventSynchronize(r.b) != hipSuccess) return HLB_EDEVICE;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return HLB_EDEVICE;
+        *launches += 1;
+        *total_ms += ms;
+    }
+    return HLB_OK;
+}
+
+hlb_status hlb_profile_reset(void) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (ProfRec &r : g_prof) {
+        (void)hipEventSynchronize(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+    return HLB_OK;
+}
+
+hlb_status hlb_release(void) {
+    if (hipDeviceSynchronize() != hipSuccess) return HLB_EDEVICE;
+    batch_release();
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HLB_EDEVICE;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+    return HLB_OK;
+}
+
+// ------------------------------- test-only helpers --------------------------------------
+
+hlb_status hlb_test_encode(const double *M, int64_t count, double delta, int64_t *out, void *stream) {
+    if (count < 0 || (count > 0 && (!M || !out))) return HLB_EINVAL;
+    if (count == 0) return HLB_OK;
+    hlb_status st = device_ready(nullptr);
+    if (st != HLB_OK) return st;
+    return launch_encode(M, count, delta, out, (hipStream_t)stream) == hipSuccess ? HLB_OK : HLB_EDEVICE;
+}
+
+// B[l] = -(A[l] S) + Menc mod q_l, or D[l] = A[l] S + B[l]: one Mod-PP-MM with the residue
+// matrix A on the left and the small signed S (mapped to residues) on the right.
+static hlb_status test_linear(int64_t rows, int64_t n, const uint64_t *A, const int64_t *S, const int64_t *Es,
+                              const uint64_t *Eu, int sign, const uint64_t *primes, int L, uint64_t *out,
+                              hipStream_t s) {
+    if (rows < 0 || n < 0 || L < 0 || (L > 0 && !primes)) return HLB_EINVAL;
+    if (rows == 0 || n == 0 || L == 0) return HLB_OK;
+    if (!A || !S || !out || (!Es && !Eu)) return HLB_EINVAL;
+    for (int l = 0; l < L; ++l)
+        if (check_modulus(primes[l]) != HLB_OK) return HLB_EINVAL;
+    hlb_status st = device_ready(nullptr);
+    if (st != HLB_OK) return st;
+    void *Sres = nullptr, *AS = nullptr;
+    if ((st = ws_alloc(&Sres, (size_t)(n * n * 8), s)) != HLB_OK) return st;
+    if ((st = ws_alloc(&AS, (size_t)(rows * n * 8), s)) != HLB_OK) {
+        ws_free(Sres, s);
+        return st;
+    }
+    for (int l = 0; l < L && st == HLB_OK; ++l) {
+        const uint64_t q = primes[l];
+        if (launch_residues_of_signed(S, n * n, q, (uint64_t *)Sres, s) != hipSuccess) {
+            st = HLB_EDEVICE;
+            break;
+        }
+        st = hlb_mod_pp_mm(q, rows, n, n, A + (int64_t)l * rows * n, n, (const uint64_t *)Sres, n,
+                           (uint64_t *)AS, n, HLB_FORM_AUTO, s);
+        if (st != HLB_OK) break;
+        if (launch_combine((const uint64_t *)AS, Es, Eu ? Eu + (int64_t)l * rows * n : nullptr, sign, rows * n, q,
+                           out + (int64_t)l * rows * n, s) != hipSuccess)
+            st = HLB_EDEVICE;
+    }
+    ws_free(Sres, s);
+    ws_free(AS, s);
+    return st;
+}
+
+hlb_status hlb_test_encrypt(int64_t k, int64_t n, const uint64_t *A, const int64_t *S, const int64_t *Menc,
+                            const uint64_t *primes, int L, uint64_t *B, void *stream) {
+    return test_linear(k, n, A, S, Menc, nullptr, -1, primes, L, B, (hipStream_t)stream);
+}
+
+hlb_status hlb_test_decrypt(int64_t rows, int64_t n, const uint64_t *A, const uint64_t *B, const int64_t *S,
+                            const uint64_t *primes, int L, uint64_t *D, void *stream) {
+    return test_linear(rows, n, A, S, nullptr, B, +1, primes, L, D, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// common.hpp -- shared definitions of the libhlb device code (gfx950 only).
+//
+// Tile geometry, the digit-plane workspace layout, modular arithmetic helpers and the kernel
+// argument structures used by the split kernels, the limb GEMMs and the host dispatcher.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hlb {
+
+// ---------------------------------------------------------------------------------------
+// Limits
+// ---------------------------------------------------------------------------------------
+constexpr int kMaxSegs = 16;          // output matrices (prime x part) per GEMM launch
+constexpr int kThreads = 256;         // 4 waves of 64 per workgroup, arranged 2 x 2
+constexpr int kBK8 = 64;              // K bytes per LDS stage (INT8 form)
+constexpr int kBK64 = 16;             // K elements per LDS stage (FP64 form)
+constexpr uint64_t kMaxModulus = (uint64_t)1 << 52;
+
+// ---------------------------------------------------------------------------------------
+// Digit-plane workspace layout (INT8 form).
+//
+// A matrix split into D balanced int8 digits is stored tile-major so that one LDS stage of
+// one workgroup is a single contiguous block:  [tile_row][k_block][digit][R][64 bytes],
+// where R (= BM for the plaintext side, BN for the ciphertext side) rows of 64 consecutive
+// K bytes form one digit plane of the tile.  For the ciphertext side a "row" is a column
+// of X (the split transposes), so both MFMA operands are K-contiguous.  Inside a row the
+// four 16-byte chunks are XOR-swizzled by swz(row) so that the MFMA fragment reads
+// (32 rows x one 16-byte chunk per wave) hit distinct LDS banks.
+// ---------------------------------------------------------------------------------------
+__host__ __device__ constexpr int swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
+// Balanced digits: x = sum_j d_j 256^j with d_j in [-128, 127].  Adding the bias
+// C_D = sum_{j<D} 128 * 256^j turns them into plain bytes u_j = d_j + 128 of x + C_D, so the
+// digits are the bytes of (x + C_D) with the top bit flipped.  x is representable with D
+// digits iff 0 <= x + C_D < 256^D.
+__host__ __device__ constexpr uint64_t digit_bias(int D) {
+    uint64_t c = 0;
+    for (int j = 0; j < D; ++j) c |= (uint64_t)0x80 << (8 * j);
+    return c;
+}
+
+// ---------------------------------------------------------------------------------------
+// Modular arithmetic (device).  q < 2^52 throughout.
+// ---------------------------------------------------------------------------------------
+
+// Canonical t mod q for a signed t with |t| < 2^62 and |t / q| < 2^49.  The quotient
+// estimate floor(t * (1/q)) carries three double roundings (relative error <= 3 * 2^-53),
+// so it is off by at most one and a single correction in each direction lands in [0, q).
+// Branch-free (selects only), so callers can be fully unrolled over register arrays.
+__device__ __forceinline__ uint64_t reduce_near(int64_t t, uint64_t q, double qinv) {
+    const double est = __builtin_floor((double)t * qinv);
+    int64_t r = t - (int64_t)est * (int64_t)q;
+    r = r < 0 ? r + (int64_t)q : r;
+    r = r >= (int64_t)q ? r - (int64_t)q : r;
+    return (uint64_t)r;
+}
+
+// Canonical c mod q for an integer-valued double |c| < 2^53.  The estimate c * (1/q) has
+// absolute error <= |c/q| * 2^-52 < 2/q <= 1, so est = floor(.) is off by at most two and
+// the exact remainder c - est * q lies in (-2q, 3q); for q >= 2^51 the error is < 2^-50 and
+// it lies in [-q, 2q).  Either way it is an integer below 2^53 in magnitude, so the fused
+// multiply-add that forms it rounds nothing, and two corrections each way finish.
+__device__ __forceinline__ uint64_t reduce_fp(double c, uint64_t q, double qd, double qinv) {
+    const double est = __builtin_floor(c * qinv);
+    double r = __builtin_fma(-est, qd, c);
+    r = r < 0.0 ? r + qd : r;
+    r = r < 0.0 ? r + qd : r;
+    r = r >= qd ? r - qd : r;
+    r = r >= qd ? r - qd : r;
+    return (uint64_t)r;
+}
+
+// a * w mod q for a constant w < q with Shoup companion wp = floor(w * 2^64 / q);
+// valid for any a < 2^64 (the result of the two wrapping products lies in [0, 2q)).
+__device__ __forceinline__ uint64_t mulmod_shoup(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+    const uint64_t hi = __umul64hi(a, wp);
+    const uint64_t r = a * w - hi * q;
+    return r >= q ? r - q : r;
+}
+
+__device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) {
+    const uint64_t s = a + b;
+    return s >= q ? s - q : s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Kernel arguments
+// ---------------------------------------------------------------------------------------
+
+// One output matrix of a launch: one (prime, part) of a CP-MM, or the single output of a
+// Mod-PP-MM.  Global column tiles [tile_begin, tile_begin + tiles) belong to it.
+struct Seg {
+    uint64_t *C;        // output, row stride ldc
+    const uint64_t *X;  // FP64 form: right operand (k x n, row stride ldx); INT8: unused
+    int64_t ldc, ldx;
+    int64_t n;          // valid columns
+    uint64_t q;
+    double qinv;        // 1.0 / q rounded to double
+    uint64_t wmod;      // 2^limb_bits mod q  (Horner multiplier)
+    uint64_t wshoup;    // floor(wmod * 2^64 / q)
+    int32_t tile_begin; // first global column tile
+    int32_t tiles;      // column tiles of this segment
+};
+
+struct GemmArgs {
+    // INT8 form: digit planes in the tile-major layout described above.
+    const int8_t *Pd;
+    const int8_t *Xd;
+    // FP64 form: the plaintext / left operand read directly (signed int64 or residues).
+    const int64_t *P;
+    int64_t ldp;
+    int64_t m;           // valid rows
+    int64_t k;           // valid K (FP64 form masks loads beyond it)
+    int32_t kblocks;     // K blocks (stages) of the launch
+    int32_t kfold;       // stages accumulated before a fold (>= kblocks: never)
+    int32_t tiles_m, tiles_n;
+    int32_t group_m;     // row tiles per raster group
+    int32_t n_xcd;       // XCDs the hardware deals workgroups to round-robin
+    int32_t limb_bits;   // FP64 form: bits per limb
+    int32_t nseg;
+    Seg seg[kMaxSegs];
+};
+
+// Maps a workgroup id to (row tile, column tile).  Workgroups are dealt to the XCDs
+// round-robin, so ids w, w+n_xcd, ... share an XCD and its L2.  The remap gives every XCD a
+// contiguous run of logical tiles, and the raster walks group_m row tiles column by column
+// within each group, so co-resident workgroups of one XCD share plaintext row panels and
+// ciphertext column panels in that L2.
+__device__ __forceinline__ void map_tile(int w, int total, int n_xcd, int tiles_m, int tiles_n,
+                                         int group_m, int &rb, int &cb) {
+    int t = w;
+    if (n_xcd > 1) {
+        const int per = total / n_xcd, rem = total % n_xcd;
+        const int x = w % n_xcd, local = w / n_xcd;
+        t = (x < rem) ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+    }
+    const int span = group_m * tiles_n;
+    const int g = t / span;
+    const int first = g * group_m;
+    const int gm = min(group_m, tiles_m - first);
+    const int in = t - g * span;
+    rb = first + in % gm;
+    cb = in / gm;
+}
+
+__device__ __forceinline__ int find_seg(const GemmArgs &a, int cb) {
+    int s = 0;
+#pragma unroll 1
+    for (int i = 1; i < a.nseg; ++i)
+        if (cb >= a.seg[i].tile_begin) s = i;
+    return s;
+}
+
+}  // namespace hlb

@@ -1,0 +1,336 @@
+// gemm_i8.hip -- INT8-digit form of the exact Mod-PP-MM on gfx950 matrix cores.
+//
+// Strategy 1 of Section 6.1 (Lemma le:strategy1, Eq decomp) with base K = 256 and balanced
+// signed digits: both operands are split into int8 digit planes, every digit-plane pair
+// P_i * X_j is multiplied exactly on v_mfma_i32_32x32x32_i8 and accumulated into the int32
+// accumulator of its shift s = i + j, and the epilogue recombines sum_s c_s 256^s and
+// reduces it modulo q (Horner, one reduction per shift) into the canonical residue.
+//
+// Exactness: a shift collects at most `pairs` digit products of magnitude <= 128*128 per K
+// element, so |c_s| <= pairs * kchunk * 2^14 < 2^31 for the K chunk the host plans; longer
+// K is cut into chunks whose partial results are folded into a 64-bit residue.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace hlb {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------------------------------
+// Digit split.  One workgroup per (tile row, k block): R rows x 64 K elements.
+//   Stage 1: each thread loads 4 consecutive K elements of one row (plaintext side: a row
+//            of P; ciphertext side: a column of X, read as 4 rows of X at one column so
+//            that lanes with consecutive columns load consecutive addresses), splits them
+//            into D digits and writes one dword (4 digit bytes) per digit into LDS.
+//   Stage 2: 16-byte chunks are copied from LDS to the swizzled tile-major workspace.
+// Entries outside the valid m x k (or k x n) range become zero digits.
+// ---------------------------------------------------------------------------------------
+constexpr int kSplitRowPad = 68;  // LDS row stride in bytes: 64 + 4 keeps dword writes conflict-free
+
+template <int D>
+__device__ __forceinline__ void digits4(const uint64_t (&x)[4], uint32_t (&out)[D]) {
+    constexpr uint64_t bias = digit_bias(D);
+    uint64_t y[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) y[e] = x[e] + bias;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w |= (uint32_t)((y[e] >> (8 * j)) & 0xffu) << (8 * e);
+        out[j] = w ^ 0x80808080u;
+    }
+}
+
+template <int D, int R>
+__device__ __forceinline__ void split_stage2(const uint8_t *lds, int8_t *tile_out) {
+    constexpr int chunks = D * R * 4;
+    static_assert(chunks % kThreads == 0, "tile chunks must divide evenly");
+#pragma unroll
+    for (int it = 0; it < chunks / kThreads; ++it) {
+        const int ci = threadIdx.x + it * kThreads;
+        const int j = ci / (R * 4);
+        const int r = (ci / 4) % R;
+        const int c = ci % 4;
+        const uint32_t *src = (const uint32_t *)(lds + (j * R + r) * kSplitRowPad + c * 16);
+        uint4 v;
+        v.x = src[0];
+        v.y = src[1];
+        v.z = src[2];
+        v.w = src[3];
+        // logical chunk c of row r lives at physical chunk c ^ swz(r)
+        *(uint4 *)(tile_out + (j * R + r) * 64 + ((c ^ swz(r)) << 4)) = v;
+    }
+}
+
+// Plaintext side: P is m x k row-major (signed int64 or residues), tile rows are rows of P.
+template <int D, int R>
+__global__ __launch_bounds__(kThreads) void split_rows_i8(const int64_t *__restrict__ P, int64_t ldp,
+                                                          int64_t m, int64_t k, int kblocks,
+                                                          int8_t *__restrict__ out) {
+    __shared__ uint8_t lds[D * R * kSplitRowPad];
+    const int rb = blockIdx.x / kblocks, kb = blockIdx.x % kblocks;
+    const int t = threadIdx.x;
+    const int quad = t & 15;  // 4 consecutive K elements
+#pragma unroll 1
+    for (int r = t >> 4; r < R; r += kThreads / 16) {
+        const int64_t row = (int64_t)rb * R + r;
+        const int64_t k0 = (int64_t)kb * kBK8 + quad * 4;
+        uint64_t x[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            x[e] = (row < m && k0 + e < k) ? (uint64_t)P[row * ldp + k0 + e] : 0;
+        uint32_t d[D];
+        digits4<D>(x, d);
+#pragma unroll
+        for (int j = 0; j < D; ++j) *(uint32_t *)(lds + (j * R + r) * kSplitRowPad + quad * 4) = d[j];
+    }
+    __syncthreads();
+    split_stage2<D, R>(lds, out + ((int64_t)rb * kblocks + kb) * (D * R * kBK8));
+}
+
+// Ciphertext side: X is k x n row-major residues, tile rows are columns of X (transposed).
+template <int D, int R>
+__global__ __launch_bounds__(kThreads) void split_cols_i8(const uint64_t *__restrict__ X, int64_t ldx,
+                                                          int64_t k, int64_t n, int kblocks,
+                                                          int8_t *__restrict__ out) {
+    __shared__ uint8_t lds[D * R * kSplitRowPad];
+    const int cb = blockIdx.x / kblocks, kb = blockIdx.x % kblocks;
+    const int t = threadIdx.x;
+    constexpr int lanes_per_row = R;              // one column per lane
+    constexpr int quads_in_flight = kThreads / R; // K quads handled per pass
+#pragma unroll 1
+    for (int qd = t / lanes_per_row; qd < 16; qd += quads_in_flight) {
+        const int c = t % lanes_per_row;
+        const int64_t col = (int64_t)cb * R + c;
+        const int64_t k0 = (int64_t)kb * kBK8 + qd * 4;
+        uint64_t x[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[e] = (col < n && k0 + e < k) ? X[(k0 + e) * ldx + col] : 0;
+        uint32_t d[D];
+        digits4<D>(x, d);
+#pragma unroll
+        for (int j = 0; j < D; ++j) *(uint32_t *)(lds + (j * R + c) * kSplitRowPad + qd * 4) = d[j];
+    }
+    __syncthreads();
+    split_stage2<D, R>(lds, out + ((int64_t)cb * kblocks + kb) * (D * R * kBK8));
+}
+
+// ---------------------------------------------------------------------------------------
+// Limb GEMM with fused recombination and mod-q epilogue.
+//   A workgroup of WAVES_M x WAVES_N waves computes a BM x BN output tile (BM = 32*WAVES_M,
+//   BN = 32*WAVES_N); each wave owns one 32 x 32 block with NS int32 accumulators per output
+//   (one per shift), i.e. 16*NS accumulator registers per lane.  K advances 64 bytes per LDS
+//   stage (two MFMA K steps of 32), double-buffered: the next stage streams from global
+//   memory straight into the other LDS buffer while the current stage's MFMAs run, with
+//   one barrier per stage.
+// ---------------------------------------------------------------------------------------
+template <int DP_, int DX_, int WAVES_M_, int WAVES_N_>
+struct I8Tile {
+    static constexpr int DP = DP_, DX = DX_, WAVES_M = WAVES_M_, WAVES_N = WAVES_N_;
+    static constexpr int NS = DP + DX - 1;
+    static constexpr int THREADS = 64 * WAVES_M * WAVES_N;
+    static constexpr int BM = 32 * WAVES_M, BN = 32 * WAVES_N;
+    static constexpr int P_TILE = DP * BM * kBK8;
+    static constexpr int X_TILE = DX * BN * kBK8;
+    static constexpr int STAGE = P_TILE + X_TILE;
+    static constexpr int P_CHUNKS = P_TILE / 16, X_CHUNKS = X_TILE / 16;
+    static_assert(P_CHUNKS % 64 == 0 && X_CHUNKS % 64 == 0, "tiles are whole wave loads");
+};
+
+// Exact integer value sum_s acc[s] 256^s reduced mod q, by Horner from the top shift:
+// r <- (256 r + c_s) mod q with r < q < 2^52 and |c_s| < 2^31, so every intermediate fits
+// in int64 and |t/q| < 2^31 meets the precondition of reduce_near.
+template <int NS>
+__device__ __forceinline__ uint64_t recombine_i8(const int (&c)[NS], uint64_t q, double qinv) {
+    uint64_t r = reduce_near((int64_t)c[NS - 1], q, qinv);
+#pragma unroll
+    for (int s = NS - 2; s >= 0; --s) r = reduce_near((int64_t)(r << 8) + (int64_t)c[s], q, qinv);
+    return r;
+}
+
+// Copies `chunks` 16-byte chunks from global memory to LDS with the gfx950 direct-to-LDS
+// load: lane l of a wave writes its 16 bytes at (wave-uniform LDS base) + 16 l, so the
+// linear chunk order of the tile-major workspace arrives unchanged and no staging
+// registers are used.  Chunks are dealt to waves in runs of 64.
+template <int THREADS, int CHUNKS>
+__device__ __forceinline__ void copy_to_lds(const int8_t *src, int8_t *dst, int tid, int wave_u) {
+#pragma unroll
+    for (int i = 0; i < (CHUNKS + THREADS - 1) / THREADS; ++i) {
+        const int base = i * THREADS + wave_u * 64;  // wave-uniform
+        if (CHUNKS % THREADS == 0 || base < CHUNKS)
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void *)(src + (i * THREADS + tid) * 16),
+                (__attribute__((address_space(3))) void *)(dst + base * 16), 16, 0, 0);
+    }
+}
+
+template <class T, bool FOLD>
+__global__ __launch_bounds__(T::THREADS, 1) void gemm_i8_kernel(const GemmArgs args) {
+    __shared__ __attribute__((aligned(16))) int8_t lds[2 * T::STAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave_u / T::WAVES_N, wn = wave_u % T::WAVES_N;
+    const int total = args.tiles_m * args.tiles_n;
+    int rb, cb;
+    map_tile(blockIdx.x, total, args.n_xcd, args.tiles_m, args.tiles_n, args.group_m, rb, cb);
+
+    const int8_t *gP = args.Pd + (int64_t)rb * args.kblocks * T::P_TILE;
+    const int8_t *gX = args.Xd + (int64_t)cb * args.kblocks * T::X_TILE;
+
+    v16i acc[T::NS];
+#pragma unroll
+    for (int s = 0; s < T::NS; ++s) acc[s] = v16i{0};
+
+    const int si = find_seg(args, cb);
+    const uint64_t q = args.seg[si].q;
+    const double qinv = args.seg[si].qinv;
+
+    // running residues of folded K chunks (only materialised when FOLD)
+    uint64_t part[FOLD ? 16 : 1];
+    if constexpr (FOLD) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) part[r] = 0;
+    }
+
+    auto gload = [&](int kb, int buf) {
+        int8_t *dp = lds + buf * T::STAGE;
+        copy_to_lds<T::THREADS, T::P_CHUNKS>(gP + (int64_t)kb * T::P_TILE, dp, tid, wave_u);
+        copy_to_lds<T::THREADS, T::X_CHUNKS>(gX + (int64_t)kb * T::X_TILE, dp + T::P_TILE, tid, wave_u);
+    };
+    auto wait_loads = [&]() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); };
+
+    // fragment addresses: this lane's row of the P tile and column of the X tile
+    const int prow = wm * 32 + (lane & 31);
+    const int xcol = wn * 32 + (lane & 31);
+    auto compute = [&](int buf) {
+        const int8_t *lp = lds + buf * T::STAGE;
+        const int8_t *lx = lp + T::P_TILE;
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int c = kk * 2 + (lane >> 5);
+            const int poff = prow * 64 + ((c ^ swz(prow)) << 4);
+            const int xoff = xcol * 64 + ((c ^ swz(xcol)) << 4);
+            v4i a[T::DP], b[T::DX];
+#pragma unroll
+            for (int i = 0; i < T::DP; ++i) a[i] = *(const v4i *)(lp + i * T::BM * 64 + poff);
+#pragma unroll
+            for (int j = 0; j < T::DX; ++j) b[j] = *(const v4i *)(lx + j * T::BN * 64 + xoff);
+#pragma unroll
+            for (int i = 0; i < T::DP; ++i)
+#pragma unroll
+                for (int j = 0; j < T::DX; ++j)
+                    acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i + j], 0, 0, 0);
+        }
+    };
+    auto fold = [&]() {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            int c[T::NS];
+#pragma unroll
+            for (int s = 0; s < T::NS; ++s) c[s] = acc[s][r];
+            part[r] = addmod(part[r], recombine_i8<T::NS>(c, q, qinv), q);
+        }
+#pragma unroll
+        for (int s = 0; s < T::NS; ++s) acc[s] = v16i{0};
+    };
+
+    const int KB = args.kblocks;
+    gload(0, 0);
+    wait_loads();
+    __syncthreads();
+#pragma unroll 1
+    for (int kb = 0; kb < KB; ++kb) {
+        const int cur = kb & 1;
+        // the other buffer was last read in iteration kb-1, which every wave has finished
+        if (kb + 1 < KB) gload(kb + 1, cur ^ 1);
+        compute(cur);
+        if constexpr (FOLD) {
+            if ((kb + 1) % args.kfold == 0 && kb + 1 < KB) fold();
+        }
+        wait_loads();
+        __syncthreads();
+    }
+
+    // Epilogue: recombine, reduce, write canonical residues (row- and column-masked).
+    const Seg &sg = args.seg[si];
+    const int64_t row0 = (int64_t)rb * T::BM + wm * 32;
+    const int64_t col = (int64_t)(cb - sg.tile_begin) * T::BN + wn * 32 + (lane & 31);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        // 32x32 accumulator layout: column = lane % 32, row = 8 (r / 4) + 4 (lane / 32) + r % 4
+        const int64_t row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        int c[T::NS];
+#pragma unroll
+        for (int s = 0; s < T::NS; ++s) c[s] = acc[s][r];
+        uint64_t v = recombine_i8<T::NS>(c, q, qinv);
+        if constexpr (FOLD) v = addmod(v, part[r], q);
+        if (row < args.m && col < sg.n) sg.C[row * sg.ldc + col] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------------------
+template <int D, int R>
+static hipError_t launch_split_rows_t(const int64_t *P, int64_t ldp, int64_t m, int64_t k,
+                                      int tiles, int kblocks, int8_t *out, hipStream_t s) {
+    hipLaunchKernelGGL((split_rows_i8<D, R>), dim3(tiles * kblocks), dim3(kThreads), 0, s, P, ldp,
+                       m, k, kblocks, out);
+    return hipGetLastError();
+}
+
+template <int D, int R>
+static hipError_t launch_split_cols_t(const uint64_t *X, int64_t ldx, int64_t k, int64_t n,
+                                      int tiles, int kblocks, int8_t *out, hipStream_t s) {
+    hipLaunchKernelGGL((split_cols_i8<D, R>), dim3(tiles * kblocks), dim3(kThreads), 0, s, X, ldx,
+                       k, n, kblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_rows_i8(int D, int R, const int64_t *P, int64_t ldp, int64_t m, int64_t k,
+                                int tiles, int kblocks, int8_t *out, hipStream_t s) {
+    if (tiles <= 0 || kblocks <= 0) return hipSuccess;
+    if (R == 128 && D == 3) return launch_split_rows_t<3, 128>(P, ldp, m, k, tiles, kblocks, out, s);
+    if (R == 64 && D == 7) return launch_split_rows_t<7, 64>(P, ldp, m, k, tiles, kblocks, out, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_split_cols_i8(int D, int R, const uint64_t *X, int64_t ldx, int64_t k, int64_t n,
+                                int tiles, int kblocks, int8_t *out, hipStream_t s) {
+    if (tiles <= 0 || kblocks <= 0) return hipSuccess;
+    if (R == 64 && D == 7) return launch_split_cols_t<7, 64>(X, ldx, k, n, tiles, kblocks, out, s);
+    if (R == 64 && D == 6) return launch_split_cols_t<6, 64>(X, ldx, k, n, tiles, kblocks, out, s);
+    return hipErrorInvalidValue;
+}
+
+template <class T, bool FOLD>
+static hipError_t launch_gemm_t(const GemmArgs &a, hipStream_t s) {
+    const int grid = a.tiles_m * a.tiles_n;
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((gemm_i8_kernel<T, FOLD>), dim3(grid), dim3(T::THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t launch_gemm_fold(const GemmArgs &a, hipStream_t s) {
+    return a.kfold < a.kblocks ? launch_gemm_t<T, true>(a, s) : launch_gemm_t<T, false>(a, s);
+}
+
+I8Shape i8_shape(int dp, int dx) {
+    if (dp == 3 && dx == 7) return {3, 7, 128, 64};
+    if (dp == 3 && dx == 6) return {3, 6, 128, 64};
+    if (dp == 7 && dx == 7) return {7, 7, 64, 64};
+    return {0, 0, 0, 0};
+}
+
+hipError_t launch_gemm_i8(int dp, int dx, const GemmArgs &a, hipStream_t s) {
+    if (dp == 3 && dx == 7) return launch_gemm_fold<I8Tile<3, 7, 4, 2>>(a, s);
+    if (dp == 3 && dx == 6) return launch_gemm_fold<I8Tile<3, 6, 4, 2>>(a, s);
+    if (dp == 7 && dx == 7) return launch_gemm_fold<I8Tile<7, 7, 2, 2>>(a, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace hlb

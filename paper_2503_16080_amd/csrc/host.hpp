@@ -1,0 +1,50 @@
+// host.hpp -- internal host-side interfaces of libhlb (planner, dispatch, profiling).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hlb.h"
+#include "common.hpp"
+
+namespace hlb {
+
+// An exact limb plan: limb counts, bits per limb and the K chunk that keeps every
+// accumulator inside the exact range of its type (Lemma le:strategy1).
+struct Plan {
+    int form = 0;
+    int np = 0, nx = 0;     // limbs of the left / right operand (instantiated counts)
+    int limb_bits = 0;
+    int pairs = 0;          // most limb products sharing one accumulator
+    int64_t kchunk = 0;     // K elements accumulated before a fold
+    int bm = 0, bn = 0, bk = 0;
+    double acc_bound_log2 = 0.0;
+};
+
+hlb_status plan(int kind, int64_t k, uint64_t qmax, int64_t pmax, int form, Plan *pl);
+hlb_status check_modulus(uint64_t q);
+hlb_status device_ready(int *n_xcd);
+void fill_seg(Seg &s, uint64_t q, int limb_bits);
+hlb_status ws_alloc(void **p, size_t bytes, hipStream_t s);
+void ws_free(void *p, hipStream_t s);
+int64_t opt_force_kchunk();
+bool opt_batch_graph();
+void batch_release();
+
+// Brackets a kernel launch with HIP events on its stream while profiling is enabled.
+class ProfScope {
+  public:
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+
+  private:
+    std::string name_;
+    hipStream_t stream_;
+    hipEvent_t a_{}, b_{};
+    bool active_ = false;
+};
+
+}  // namespace hlb

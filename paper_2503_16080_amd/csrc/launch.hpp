@@ -1,0 +1,43 @@
+// launch.hpp -- host-side launchers of the libhlb kernels (internal interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace hlb {
+
+// Tile shape of an INT8 GEMM instantiation: digits of each operand and workgroup tile.
+struct I8Shape {
+    int dp, dx;  // 0 when no instantiation exists
+    int bm, bn;
+};
+I8Shape i8_shape(int dp, int dx);
+
+// Digit split of the left operand (rows of P) into the tile-major workspace.
+hipError_t launch_split_rows_i8(int D, int R, const int64_t *P, int64_t ldp, int64_t m, int64_t k,
+                                int tiles, int kblocks, int8_t *out, hipStream_t s);
+// Digit split of the right operand (columns of X, transposed) into the workspace.
+hipError_t launch_split_cols_i8(int D, int R, const uint64_t *X, int64_t ldx, int64_t k, int64_t n,
+                                int tiles, int kblocks, int8_t *out, hipStream_t s);
+hipError_t launch_gemm_i8(int dp, int dx, const GemmArgs &a, hipStream_t s);
+
+// FP64 form: limb counts of each operand; returns false when no instantiation exists.
+bool f64_supported(int np, int nx);
+hipError_t launch_gemm_f64(int np, int nx, const GemmArgs &a, hipStream_t s);
+
+// Auxiliary kernels.
+hipError_t launch_validate(const uint64_t *X, int64_t rows, int64_t cols, int64_t ld, uint64_t q,
+                           unsigned long long *first_bad, hipStream_t s);
+hipError_t launch_absmax(const int64_t *P, int64_t m, int64_t k, int64_t ld,
+                         unsigned long long *out, hipStream_t s);
+hipError_t launch_encode(const double *M, int64_t count, double delta, int64_t *out, hipStream_t s);
+// D[i] = (sign * AS[i] + E[i]) mod q elementwise over `count` entries, with AS residues and
+// E signed: used by the test-only encrypt (sign = -1) and decrypt (sign = +1, E = residues).
+hipError_t launch_combine(const uint64_t *AS, const int64_t *Es, const uint64_t *Eu, int sign,
+                          int64_t count, uint64_t q, uint64_t *out, hipStream_t s);
+hipError_t launch_residues_of_signed(const int64_t *v, int64_t count, uint64_t q, uint64_t *out,
+                                     hipStream_t s);
+
+}  // namespace hlb

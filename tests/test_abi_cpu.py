@@ -1,0 +1,139 @@
+"""CPU-only checks of the C ABI: the library loads, exports every declared symbol, and its
+host logic (argument checks, exactness planner) behaves as documented -- no device calls."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_2503_16080_amd as hlb
+import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hlb.h")
+
+Q50 = wl.ntt_primes(50, 1)[0]  # the largest 50-bit prime = 1 (mod 2^17)
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hlb_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hlb.load()
+    names = _declared()
+    assert "hlb_cp_mm" in names and "hlb_mod_pp_mm" in names and "hlb_cp_mm_batch" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    assert hlb.hlb_status_str(0) == "ok"
+    assert "invalid" in hlb.hlb_status_str(1)
+    assert hlb.hlb_status_str(99) == "unknown status"
+
+
+def test_plan_int8_cpmm_matches_bounds():
+    p = hlb.plan(1, 8192, Q50, 1 << 20, "int8")
+    assert (p["form"], p["p_limbs"], p["x_limbs"], p["shifts"], p["limb_bits"]) == (2, 3, 7, 9, 8)
+    # |c_s| <= pairs * k_chunk * 128^2 < 2^31, chunk a whole number of 64-byte K stages
+    assert p["max_pairs"] == 3
+    assert p["k_chunk"] % 64 == 0
+    assert p["max_pairs"] * p["k_chunk"] * 128 * 128 < 2 ** 31
+    assert p["max_pairs"] * (p["k_chunk"] + 64) * 128 * 128 >= 2 ** 31  # largest such chunk
+    assert p["k_chunk"] >= 16384   # no fold for any benchmark shape
+    assert p["acc_bound_log2"] < 31
+
+
+def test_plan_int8_digit_counts():
+    # 45-bit primes need 6 balanced digits (capacity 127 * (256^6 - 1) / 255 ~ 2^47)
+    p = hlb.plan(1, 4096, (1 << 45) - 55, 1 << 20, "int8")
+    assert (p["p_limbs"], p["x_limbs"]) == (3, 6)
+    # a plaintext beyond 3 digits (capacity 8355711) or a full residue uses 7 x 7
+    p = hlb.plan(1, 4096, Q50, 8355712, "int8")
+    assert (p["p_limbs"], p["x_limbs"]) == (7, 7)
+    p = hlb.plan(0, 256, Q50, 1, "int8")
+    assert (p["p_limbs"], p["x_limbs"], p["shifts"], p["max_pairs"]) == (7, 7, 13, 7)
+    assert 7 * p["k_chunk"] * 16384 < 2 ** 31
+    cap = lambda D: 127 * (256 ** D - 1) // 255
+    for q in [3, 97, 1 << 20, (1 << 45) + 1, Q50, (1 << 52) - 1]:
+        p = hlb.plan(0, 64, q, 1, "int8")
+        assert cap(p["x_limbs"]) >= q - 1
+
+
+def test_plan_fp64_paper_form():
+    # one plaintext limb (k2 = 1) and three ciphertext limbs (k1 = 3), as in Section 6.3
+    p = hlb.plan(1, 8192, Q50, 1 << 20, "fp64")
+    assert (p["form"], p["p_limbs"], p["x_limbs"]) == (1, 1, 3)
+    w = p["limb_bits"]
+    assert 3 * w >= 50
+    assert p["k_chunk"] * (1 << 20) * ((1 << w) - 1) < 2 ** 53
+    assert p["k_chunk"] >= 16384
+    # general Mod-PP-MM: both operands in L limbs, L * k * (2^w - 1)^2 < 2^53
+    p = hlb.plan(0, 256, Q50, 1, "fp64")
+    L, w = p["p_limbs"], p["limb_bits"]
+    assert L == p["x_limbs"] and L * w >= 50
+    assert L * p["k_chunk"] * ((1 << w) - 1) ** 2 < 2 ** 53
+
+
+def test_plan_auto_prefers_int8_and_forced_chunk():
+    assert hlb.plan(1, 4096, Q50, 1 << 20, "auto")["form"] == hlb.FORM_INT8
+    try:
+        hlb.set_option(hlb.OPT_FORCE_KCHUNK, 200)
+        assert hlb.plan(1, 4096, Q50, 1 << 20, "int8")["k_chunk"] == 192
+        assert hlb.plan(1, 4096, Q50, 1 << 20, "fp64")["k_chunk"] == 192
+    finally:
+        hlb.set_option(hlb.OPT_FORCE_KCHUNK, 0)
+    assert hlb.plan(1, 4096, Q50, 1 << 20, "int8")["k_chunk"] > 4096
+
+
+def test_plan_rejects_bad_arguments():
+    lib = hlb.load()
+    d = hlb.PlanDesc()
+    for args in [(2, 64, Q50, 1, 0), (0, -1, Q50, 1, 0), (0, 64, 1, 1, 0), (0, 64, 1 << 52, 1, 0),
+                 (1, 64, Q50, 0, 0), (1, 64, Q50, 1 << 52, 0), (0, 64, Q50, 1, 7)]:
+        assert lib.hlb_plan(*args, ctypes.byref(d)) == 1, args
+
+
+def test_entry_points_reject_bad_arguments_before_device_work():
+    lib = hlb.load()
+    fake = 0x1000  # never dereferenced: every call below fails validation first
+    # modulus out of range
+    assert lib.hlb_mod_pp_mm(1, 4, 4, 4, fake, 4, fake, 4, fake, 4, 0, None) == 1
+    assert lib.hlb_mod_pp_mm(1 << 52, 4, 4, 4, fake, 4, fake, 4, fake, 4, 0, None) == 1
+    # negative sizes, short leading dimensions, null pointers
+    assert lib.hlb_mod_pp_mm(97, -1, 4, 4, fake, 4, fake, 4, fake, 4, 0, None) == 1
+    assert lib.hlb_mod_pp_mm(97, 4, 4, 4, fake, 3, fake, 4, fake, 4, 0, None) == 1
+    assert lib.hlb_mod_pp_mm(97, 4, 4, 4, fake, 4, fake, 4, None, 4, 0, None) == 1
+    assert lib.hlb_mod_pp_mm(97, 4, 4, 4, None, 4, fake, 4, fake, 4, 0, None) == 1
+    # empty products are no-ops that touch nothing
+    assert lib.hlb_mod_pp_mm(97, 0, 4, 4, None, 4, None, 4, None, 4, 0, None) == 0
+    assert lib.hlb_mod_pp_mm(97, 4, 4, 0, None, 4, None, 4, None, 4, 0, None) == 0
+    qs = (ctypes.c_uint64 * 2)(Q50, 1)
+    assert lib.hlb_cp_mm(4, 4, 4, 4, fake, 4, 8, fake, fake, qs, 2, fake, fake, 2, None) == 1
+    qs = (ctypes.c_uint64 * 1)(Q50)
+    assert lib.hlb_cp_mm(4, 4, 4, 4, fake, 4, -1, fake, fake, qs, 1, fake, fake, 2, None) == 1
+    assert lib.hlb_cp_mm(4, 4, 4, 4, fake, 4, 1 << 52, fake, fake, qs, 1, fake, fake, 2, None) == 1
+    assert lib.hlb_cp_mm(4, 4, 4, 4, fake, 2, 8, fake, fake, qs, 1, fake, fake, 2, None) == 1
+    assert lib.hlb_cp_mm(4, 4, 4, 4, fake, 4, 8, fake, fake, None, 1, fake, fake, 2, None) == 1
+    assert lib.hlb_cp_mm(4, 4, 4, 4, fake, 4, 8, fake, fake, qs, 0, fake, fake, 2, None) == 0
+    assert lib.hlb_cp_mm(0, 4, 4, 4, fake, 4, 8, fake, fake, qs, 1, fake, fake, 2, None) == 0
+    assert lib.hlb_cp_mm(4, 4, 4, 4, fake, 4, 8, fake, fake, qs, 1, None, fake, 2, None) == 1
+    assert lib.hlb_cp_mm_batch(None, 3, qs, 1, 2, None) == 1
+    assert lib.hlb_cp_mm_batch(None, 0, qs, 1, 2, None) == 0
+    bad = ctypes.c_int64(0)
+    assert lib.hlb_validate_residues(fake, 4, 4, 3, 97, ctypes.byref(bad), None) == 1
+    assert lib.hlb_validate_residues(fake, 0, 4, 4, 97, ctypes.byref(bad), None) == 0
+    assert bad.value == -1
+    assert lib.hlb_set_option(999, 1) == 6
+    assert lib.hlb_set_option(hlb.OPT_FORCE_KCHUNK, -5) == 1
+
+
+def test_no_silent_fallback_without_library(monkeypatch):
+    monkeypatch.setattr(hlb, "_lib", None)
+    monkeypatch.setattr(hlb, "_LIB_PATH", "/nonexistent/libhlb.so")
+    with pytest.raises(hlb.HlbError):
+        hlb.load()
