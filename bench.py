@@ -1,0 +1,176 @@
+"""Benchmark of the CP-MM hot path on one MI355X.
+
+Default workload: CP-MM at d = 8192 -- an 8192 x 8192 plaintext P = floor(2^20 U + 1/2)
+times a ciphertext whose a- and b-parts are 8192 x 8192 residue matrices, over 3 RNS primes
+of 50 bits -- in the INT8-limb form.  One step is one full ``hlb_cp_mm`` call: plaintext
+digit split, ciphertext digit split (all primes and parts), and one limb-GEMM launch with the
+fused recombination / mod-q epilogue, i.e. 2 * L = 6 Mod-PP-MMs of 8192^3.
+
+Reported: mod-q MACs/s (2 L m k n per step / step time), the same workload in the FP64-limb
+form, a same-shape vendor FP64 GEMM (torch float64 matmul, d^3) and the resulting slowdown,
+the limb GEMM's roofline position (HIP events around its launches, inside the timed region),
+and the CPU oracle's rate on a bounded row sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "CP-MM mod-q MACs/s at d=8192, INT8-limb vs FP64-limb; ratio to FP64 GEMM"
+INT8_PEAK_TOPS = 5000.0     # MI355X dense INT8 matrix peak, 5.0 POP/s
+FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--d", type=int, default=8192, help="matrix size (default 8192)")
+    ap.add_argument("--primes", type=int, default=3)
+    ap.add_argument("--bits", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-limb and dgemm legs")
+    return ap.parse_args()
+
+
+def _time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(w, target_s=15.0):
+    """The oracle timed on a bounded row sample of the same CP-MM (all primes, both parts)."""
+    import oracle
+    m, k, nA, nB, L = w.m, w.k, w.nA, w.nB, len(w.primes)
+    per_row = L * k * (nA + nB)
+    t0 = time.perf_counter()
+    oracle.cp_mm(w.P, w.A, w.B, w.primes, rows=[0])
+    t1 = time.perf_counter() - t0
+    rows = int(max(1, min(m, target_s / max(t1, 1e-3))))
+    sample = list(range(0, m, max(1, m // rows)))[:rows]
+    t0 = time.perf_counter()
+    oracle.cp_mm(w.P, w.A, w.B, w.primes, rows=sample)
+    dt = time.perf_counter() - t0
+    return {"value": len(sample) * per_row / dt, "unit": "mod-q MAC/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{len(sample)} of {m} output rows of the CP-MM (all {L} primes, a- and "
+                      f"b-parts), {dt:.1f} s; rate scales linearly with rows"}
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the CP-MM path has no multi-GPU leg); "
+              f"got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2503_16080_amd as hlb
+    import workloads as wl
+
+    d, L = args.d, args.primes
+    seed = 1003
+    w = wl.cpmm_uniform(seed, d, d, d, args.bits, L)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev)
+    P, A, B = t(w.P), t(w.A), t(w.B)
+    PA = torch.empty((L, d, d), dtype=torch.int64, device=dev)
+    PB = torch.empty((L, d, d), dtype=torch.int64, device=dev)
+    macs = 2 * L * d * d * d  # mod-q MACs per step
+
+    def step(form):
+        return lambda: hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form=form, out=(PA, PB))
+
+    # INT8-limb form: the headline, with the limb GEMM's launches bracketed by HIP events
+    for _ in range(args.warmup):
+        step("int8")()
+    torch.cuda.synchronize()
+    hlb.profile_reset()
+    hlb.set_option(hlb.OPT_PROFILE, 1)
+    s_int8 = _time_steps(step("int8"), args.steps, 0)
+    hlb.set_option(hlb.OPT_PROFILE, 0)
+    n_gemm, ms_gemm = hlb.profile_read("gemm_i8")
+    n_sp, ms_sp = hlb.profile_read("split_p")
+    n_sx, ms_sx = hlb.profile_read("split_x")
+    hlb.profile_reset()
+    gemm_ms = ms_gemm / max(n_gemm, 1)
+    plan = hlb.plan(1, d, max(w.primes), w.p_absmax, "int8")
+    limb_products = plan["p_limbs"] * plan["x_limbs"]
+    # algorithmic int8 ops of one launch: 2 per MAC, limb_products MACs per mod-q MAC
+    ops = 2.0 * limb_products * macs
+    achieved_tops = ops / (gemm_ms * 1e-3) / 1e12
+
+    out = {
+        "metric": METRIC,
+        "value": macs / s_int8,
+        "unit": "mod-q MAC/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": s_int8 * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i8", "data": "synthetic",
+        "config": {"workload": f"cp_mm d={d}: {d}x{d} plaintext (|P|<=2^20) times {d}x{d} a- and "
+                               f"b-parts over {L} RNS primes of {args.bits} bits, INT8-limb form",
+                   "m": d, "k": d, "n": d, "primes": L, "prime_bits": args.bits, "form": "int8",
+                   "digits": [plan["p_limbs"], plan["x_limbs"]]},
+        "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": INT8_PEAK_TOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tops / INT8_PEAK_TOPS, "traffic": None,
+                     "kernel": "gemm_i8_kernel", "avg_launch_ms": gemm_ms, "launches": n_gemm,
+                     "ops_per_launch": ops, "op": "int8 MAC x 2"},
+        "kernels_ms": {"gemm_i8": gemm_ms, "split_p": ms_sp / max(n_sp, 1),
+                       "split_x_per_matrix": ms_sx / max(n_sx, 1)},
+    }
+
+    if not args.no_fp64:
+        fp_steps = max(2, args.steps // 3)
+        hlb.profile_reset()
+        step("fp64")()
+        torch.cuda.synchronize()
+        hlb.set_option(hlb.OPT_PROFILE, 1)
+        s_fp64 = _time_steps(step("fp64"), fp_steps, 0)
+        hlb.set_option(hlb.OPT_PROFILE, 0)
+        n_f, ms_f = hlb.profile_read("gemm_f64")
+        hlb.profile_reset()
+        fplan = hlb.plan(1, d, max(w.primes), w.p_absmax, "fp64")
+        f_ops = 2.0 * fplan["p_limbs"] * fplan["x_limbs"] * macs
+        f_tf = f_ops / (ms_f / max(n_f, 1) * 1e-3) / 1e12
+        # same-shape cleartext FP64 GEMM (vendor library through torch): d x d x d
+        Xf = torch.rand((d, d), dtype=torch.float64, device=dev)
+        Yf = torch.rand((d, d), dtype=torch.float64, device=dev)
+        Zf = torch.empty((d, d), dtype=torch.float64, device=dev)
+        s_dgemm = _time_steps(lambda: torch.matmul(Xf, Yf, out=Zf), max(3, args.steps // 2), 2)
+        del Xf, Yf, Zf
+        out["fp64_form"] = {"value": macs / s_fp64, "unit": "mod-q MAC/s", "ms_per_step": s_fp64 * 1e3,
+                            "limbs": [fplan["p_limbs"], fplan["x_limbs"]], "limb_bits": fplan["limb_bits"],
+                            "gemm_tflops": f_tf, "gemm_frac_of_fp64_peak": f_tf / FP64_PEAK_TFLOPS}
+        out["fp64_gemm"] = {"ms": s_dgemm * 1e3, "tflops": 2.0 * d ** 3 / s_dgemm / 1e12,
+                            "shape": f"{d}x{d}x{d}", "impl": "torch.matmul float64"}
+        out["int8_vs_fp64_form_speedup"] = s_fp64 / s_int8
+        out["slowdown_vs_fp64_gemm"] = {"int8_form": s_int8 / s_dgemm, "fp64_form": s_fp64 / s_dgemm}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
