@@ -40,6 +40,9 @@ def _parse():
     ap.add_argument("--bits", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-limb and dgemm legs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run 3 device-to-device copies of 1 GiB (a reference kernel of "
+                         "known traffic for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -86,6 +89,14 @@ def main():
 
     import paper_2503_16080_amd as hlb
     import workloads as wl
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.int64, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     d, L = args.d, args.primes
     seed = 1003

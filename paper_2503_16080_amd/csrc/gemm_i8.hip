@@ -166,9 +166,57 @@ __device__ __forceinline__ void copy_to_lds(const int8_t *src, int8_t *dst, int 
     }
 }
 
+// s_waitcnt vmcnt(n) for a wave-uniform n known only at run time (the immediate must be a
+// constant, so the possible counts are enumerated).
+__device__ __forceinline__ void wait_vmcnt(int n) {
+    switch (n) {
+        case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+        case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
+        case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+        case 3: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
+        case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+        case 5: asm volatile("s_waitcnt vmcnt(5)" ::: "memory"); break;
+        case 6: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
+        case 7: asm volatile("s_waitcnt vmcnt(7)" ::: "memory"); break;
+        case 8: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+        case 9: asm volatile("s_waitcnt vmcnt(9)" ::: "memory"); break;
+        case 10: asm volatile("s_waitcnt vmcnt(10)" ::: "memory"); break;
+        case 11: asm volatile("s_waitcnt vmcnt(11)" ::: "memory"); break;
+        case 12: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
+        case 13: asm volatile("s_waitcnt vmcnt(13)" ::: "memory"); break;
+        case 14: asm volatile("s_waitcnt vmcnt(14)" ::: "memory"); break;
+        default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    }
+}
+
+// Direct-to-LDS loads a wave issues for one stage (chunks are dealt in runs of 64).
+template <int THREADS, int CHUNKS>
+__device__ __forceinline__ int loads_of_wave(int wave_u) {
+    int n = 0;
+#pragma unroll
+    for (int i = 0; i < (CHUNKS + THREADS - 1) / THREADS; ++i) n += (i * THREADS + wave_u * 64 < CHUNKS);
+    return n;
+}
+
+constexpr int kLdsBytes = 160 * 1024;
+
+// Workgroup barrier WITHOUT the memory fence of __syncthreads(): that fence waits for every
+// outstanding global load (vmcnt(0)), which would also wait for the direct-to-LDS loads of
+// the stages still in flight.  Visibility is handled explicitly instead: each wave waits
+// (wait_vmcnt) for the loads of the stage about to be read, and its own LDS reads of the
+// stage about to be overwritten have completed because the MFMAs consumed them.
+__device__ __forceinline__ void stage_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 template <class T, bool FOLD>
 __global__ __launch_bounds__(T::THREADS, 1) void gemm_i8_kernel(const GemmArgs args) {
-    __shared__ __attribute__((aligned(16))) int8_t lds[2 * T::STAGE];
+    // Three LDS stages when they fit: global loads then have two stages of compute to land
+    // instead of one.
+    constexpr int NBUF = 3 * T::STAGE <= kLdsBytes ? 3 : 2;
+    __shared__ __attribute__((aligned(16))) int8_t lds[NBUF * T::STAGE];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -200,30 +248,35 @@ __global__ __launch_bounds__(T::THREADS, 1) void gemm_i8_kernel(const GemmArgs a
         copy_to_lds<T::THREADS, T::P_CHUNKS>(gP + (int64_t)kb * T::P_TILE, dp, tid, wave_u);
         copy_to_lds<T::THREADS, T::X_CHUNKS>(gX + (int64_t)kb * T::X_TILE, dp + T::P_TILE, tid, wave_u);
     };
-    auto wait_loads = [&]() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); };
+    const int loads_per_stage = loads_of_wave<T::THREADS, T::P_CHUNKS>(wave_u) +
+                                loads_of_wave<T::THREADS, T::X_CHUNKS>(wave_u);
 
     // fragment addresses: this lane's row of the P tile and column of the X tile
     const int prow = wm * 32 + (lane & 31);
     const int xcol = wn * 32 + (lane & 31);
-    auto compute = [&](int buf) {
+    // One K half (32 bytes) of a stage: the DP plaintext and DX ciphertext fragments of this
+    // lane, then the DP x DX digit-pair MFMAs into the shift accumulators.
+    using Frags = struct {
+        v4i a[T::DP];
+        v4i b[T::DX];
+    };
+    auto read_frags = [&](Frags &f, int buf, int kk) {
         const int8_t *lp = lds + buf * T::STAGE;
         const int8_t *lx = lp + T::P_TILE;
+        const int c = kk * 2 + (lane >> 5);
+        const int poff = prow * 64 + ((c ^ swz(prow)) << 4);
+        const int xoff = xcol * 64 + ((c ^ swz(xcol)) << 4);
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-            const int c = kk * 2 + (lane >> 5);
-            const int poff = prow * 64 + ((c ^ swz(prow)) << 4);
-            const int xoff = xcol * 64 + ((c ^ swz(xcol)) << 4);
-            v4i a[T::DP], b[T::DX];
+        for (int i = 0; i < T::DP; ++i) f.a[i] = *(const v4i *)(lp + i * T::BM * 64 + poff);
 #pragma unroll
-            for (int i = 0; i < T::DP; ++i) a[i] = *(const v4i *)(lp + i * T::BM * 64 + poff);
+        for (int j = 0; j < T::DX; ++j) f.b[j] = *(const v4i *)(lx + j * T::BN * 64 + xoff);
+    };
+    auto mfmas = [&](const Frags &f) {
 #pragma unroll
-            for (int j = 0; j < T::DX; ++j) b[j] = *(const v4i *)(lx + j * T::BN * 64 + xoff);
+        for (int i = 0; i < T::DP; ++i)
 #pragma unroll
-            for (int i = 0; i < T::DP; ++i)
-#pragma unroll
-                for (int j = 0; j < T::DX; ++j)
-                    acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i + j], 0, 0, 0);
-        }
+            for (int j = 0; j < T::DX; ++j)
+                acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a[i], f.b[j], acc[i + j], 0, 0, 0);
     };
     auto fold = [&]() {
 #pragma unroll
@@ -237,21 +290,42 @@ __global__ __launch_bounds__(T::THREADS, 1) void gemm_i8_kernel(const GemmArgs a
         for (int s = 0; s < T::NS; ++s) acc[s] = v16i{0};
     };
 
+    // Pipeline (per wave), half a stage deep in registers and NBUF stages deep in LDS:
+    //   read F1 = (kb, second half) | MFMAs on F0 | wait: F1 read, stage kb+1 landed |
+    //   barrier | DMA stage kb+NBUF into the buffer of stage kb | read F0 = (kb+1, first half) |
+    //   MFMAs on F1
+    // so every LDS read overlaps a half stage of MFMAs, and every stage's global loads have
+    // NBUF-1 stages of compute to land.  At the barrier all waves have finished reading the
+    // buffer of stage kb (hence it can be refilled) and have seen stage kb+1 land.
     const int KB = args.kblocks;
-    gload(0, 0);
-    wait_loads();
-    __syncthreads();
+    // loads still allowed in flight when stage `need` must have landed, given that stages
+    // up to min(KB-1, issued_hi) have been issued
+    auto outstanding = [&](int need, int issued_hi) {
+        const int ahead = min(KB - 1, issued_hi) - need;
+        return ahead > 0 ? ahead * loads_per_stage : 0;
+    };
+#pragma unroll
+    for (int st = 0; st < NBUF; ++st)
+        if (st < KB) gload(st, st);
+    wait_vmcnt(outstanding(0, NBUF - 1));
+    stage_barrier();
+    Frags f0, f1;
+    read_frags(f0, 0, 0);
 #pragma unroll 1
     for (int kb = 0; kb < KB; ++kb) {
-        const int cur = kb & 1;
-        // the other buffer was last read in iteration kb-1, which every wave has finished
-        if (kb + 1 < KB) gload(kb + 1, cur ^ 1);
-        compute(cur);
+        const int cur = kb % NBUF;
+        read_frags(f1, cur, 1);
+        mfmas(f0);
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        // stages issued so far: up to kb + NBUF - 1
+        wait_vmcnt(outstanding(kb + 1, kb + NBUF - 1));
+        stage_barrier();
+        if (kb + NBUF < KB) gload(kb + NBUF, cur);
+        if (kb + 1 < KB) read_frags(f0, (kb + 1) % NBUF, 0);
+        mfmas(f1);
         if constexpr (FOLD) {
             if ((kb + 1) % args.kfold == 0 && kb + 1 < KB) fold();
         }
-        wait_loads();
-        __syncthreads();
     }
 
     // Epilogue: recombine, reduce, write canonical residues (row- and column-masked).
