@@ -152,10 +152,28 @@ typedef enum {
     HLB_OPT_FORCE_KCHUNK = 1, /* >0: cap the fold chunk at this many K elements (rounded to
                                  the kernel's K step); 0 restores the planned chunk */
     HLB_OPT_PROFILE = 2,      /* 1: bracket every kernel launch with HIP events */
-    HLB_OPT_BATCH_GRAPH = 3   /* 1 (default): capture/replay batches as HIP graphs; 0: eager */
+    HLB_OPT_BATCH_GRAPH = 3,  /* 1 (default): capture/replay batches as HIP graphs; 0: eager */
+    HLB_OPT_FORCE_CLASS = 4   /* INT8 tile class: -1 (default) = tuned/heuristic choice,
+                                 0 = 128 x 64 output tiles, 1 = 64 x 128 output tiles */
 } hlb_option;
 
 hlb_status hlb_set_option(int option, int64_t value);
+
+/*
+ * Tile-class tuning table (host only).  The INT8 form has two workgroup tile classes; the
+ * planner picks one per problem from this table, keyed by the ciphertext digit count and
+ * the floor(log2) of the problem's rows m, columns n (of one output matrix) and depth k,
+ * falling back to a padding-waste heuristic for keys it does not hold.  The autotuner
+ * (paper_2503_16080_amd.autotune) measures both classes per key and fills the table.
+ *   hlb_tune_set:   sets one entry (cls 0 or 1; cls -1 erases it).
+ *   hlb_tune_load:  reads entries "x_digits log2m log2n log2k cls" (one per line, '#'
+ *                   comments) from a text file; the library also loads the file named by
+ *                   the environment variable HLB_TUNE_CACHE on first use.
+ *   hlb_tune_class: the class the planner would use for a shape (-1 if none applies).
+ */
+hlb_status hlb_tune_set(int x_digits, int log2m, int log2n, int log2k, int cls);
+hlb_status hlb_tune_load(const char *path);
+int hlb_tune_class(int x_digits, int64_t m, int64_t n, int64_t k);
 
 /*
  * Kernel timing collected while HLB_OPT_PROFILE is on (synchronous: waits for the

@@ -23,14 +23,14 @@ __all__ = [
     "hlb_mod_pp_mm", "hlb_cp_mm", "hlb_cp_mm_batch", "hlb_validate_residues",
     "hlb_plaintext_absmax", "hlb_plan", "hlb_set_option", "hlb_profile_read",
     "hlb_profile_reset", "hlb_release", "hlb_status_str", "hlb_test_encode",
-    "hlb_test_encrypt", "hlb_test_decrypt",
+    "hlb_test_encrypt", "hlb_test_decrypt", "hlb_tune_set", "hlb_tune_load", "hlb_tune_class",
     "mod_pp_mm", "cp_mm", "cp_mm_batch", "validate_residues", "plaintext_absmax", "plan",
     "set_option", "profile_read", "profile_reset", "release",
 ]
 
 FORM_AUTO, FORM_FP64, FORM_INT8 = 0, 1, 2
 _FORMS = {"auto": FORM_AUTO, "fp64": FORM_FP64, "int8": FORM_INT8}
-OPT_FORCE_KCHUNK, OPT_PROFILE, OPT_BATCH_GRAPH = 1, 2, 3
+OPT_FORCE_KCHUNK, OPT_PROFILE, OPT_BATCH_GRAPH, OPT_FORCE_CLASS = 1, 2, 3, 4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libhlb.so")
@@ -91,6 +91,9 @@ def load():
             "hlb_test_encode": (ci, [vp, i64, ctypes.c_double, vp, vp]),
             "hlb_test_encrypt": (ci, [i64, i64, vp, vp, vp, vp, ci, vp, vp]),
             "hlb_test_decrypt": (ci, [i64, i64, vp, vp, vp, vp, ci, vp, vp]),
+            "hlb_tune_set": (ci, [ci, ci, ci, ci, ci]),
+            "hlb_tune_load": (ci, [ctypes.c_char_p]),
+            "hlb_tune_class": (ci, [ci, i64, i64, i64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -129,6 +132,8 @@ def _dev64(t: torch.Tensor, name: str) -> torch.Tensor:
 
 
 def _row_stride(t: torch.Tensor, name: str) -> int:
+    if t.dim() == 2 and t.numel() == 0:
+        return t.shape[1]  # no element is addressed; any stride >= the row length is valid
     if t.dim() != 2 or t.stride(1) != 1:
         raise ValueError(f"{name} must be a 2-D row-major view (unit column stride)")
     return max(t.stride(0), t.shape[1])
@@ -265,6 +270,19 @@ def hlb_profile_reset():
 
 def hlb_release():
     _check(load().hlb_release(), "release")
+
+
+def hlb_tune_set(x_digits: int, log2m: int, log2n: int, log2k: int, cls: int):
+    _check(load().hlb_tune_set(int(x_digits), int(log2m), int(log2n), int(log2k), int(cls)), "tune_set")
+
+
+def hlb_tune_load(path: str):
+    _check(load().hlb_tune_load(path.encode()), "tune_load")
+
+
+def hlb_tune_class(x_digits: int, m: int, n: int, k: int) -> int:
+    """INT8 tile class the planner picks for an m x n (one output matrix) x k problem."""
+    return int(load().hlb_tune_class(int(x_digits), int(m), int(n), int(k)))
 
 
 # ------------------------------------------------------------------------------------------

@@ -8,6 +8,8 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <cstdio>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -25,6 +27,7 @@ namespace hlb {
 static std::atomic<int64_t> g_force_kchunk{0};
 static std::atomic<int> g_profile{0};
 static std::atomic<int> g_batch_graph{1};
+static std::atomic<int> g_force_class{-1};
 
 int64_t opt_force_kchunk() { return g_force_kchunk.load(); }
 bool opt_batch_graph() { return g_batch_graph.load() != 0; }
@@ -38,6 +41,8 @@ static std::vector<ProfRec> g_prof;
 
 ProfScope::ProfScope(const char *name, hipStream_t s) : stream_(s) {
     if (!g_profile.load()) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     name_ = name;
     if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) return;
     if (hipEventRecord(a_, s) != hipSuccess) return;
@@ -100,6 +105,8 @@ static int i8_digits(uint64_t vmax) {
         if (vmax <= i8_capacity(D)) return D;
     return 8;
 }
+int i8_digits_for(uint64_t vmax) { return i8_digits(vmax); }
+
 static int bit_length(uint64_t v) {
     int b = 0;
     while (v) {
@@ -124,7 +131,7 @@ hlb_status plan_i8(int kind, int64_t k, uint64_t qmax, int64_t pmax, Plan *pl) {
     else if (dp <= 3 && dx == 7) ip = 3, ix = 7;
     else if (dp <= 7 && dx <= 7) ip = 7, ix = 7;
     else return HLB_EBOUND;
-    const I8Shape sh = i8_shape(ip, ix);
+    const I8Shape sh = i8_shape(ip, ix, 0);
     if (!sh.dp) return HLB_EBOUND;
     const int pairs = std::min(ip, ix);
     // |c_s| <= pairs * kchunk * 128 * 128 must stay <= 2^31 - 1
@@ -206,6 +213,61 @@ hlb_status plan(int kind, int64_t k, uint64_t qmax, int64_t pmax, int form, Plan
         return plan_f64(kind, k, qmax, pmax, pl);
     }
     return HLB_EINVAL;
+}
+
+// ---------------------------------------------------------------------------------------
+// Tile-class tuning table: (x digits, log2 m, log2 n, log2 k) -> class.
+// ---------------------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<uint32_t, int> g_tune;
+static bool g_tune_env_loaded = false;
+
+static int floor_log2(int64_t v) { return v <= 1 ? 0 : 63 - __builtin_clzll((unsigned long long)v); }
+static uint32_t tune_key(int dx, int lm, int ln, int lk) {
+    return ((uint32_t)(dx & 0xff) << 24) | ((uint32_t)(lm & 0x3f) << 12) | ((uint32_t)(ln & 0x3f) << 6) |
+           (uint32_t)(lk & 0x3f);
+}
+static hlb_status tune_load_locked(const char *path) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return HLB_EINVAL;
+    char line[256];
+    while (std::fgets(line, sizeof(line), f)) {
+        if (line[0] == '#') continue;
+        int dx, lm, ln, lk, c;
+        if (std::sscanf(line, "%d %d %d %d %d", &dx, &lm, &ln, &lk, &c) == 5 && (c == 0 || c == 1))
+            g_tune[tune_key(dx, lm, ln, lk)] = c;
+    }
+    std::fclose(f);
+    return HLB_OK;
+}
+static int tune_lookup(int dx, int64_t m, int64_t n, int64_t k) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (!g_tune_env_loaded) {
+        g_tune_env_loaded = true;
+        const char *env = std::getenv("HLB_TUNE_CACHE");
+        if (env && *env) (void)tune_load_locked(env);
+    }
+    auto it = g_tune.find(tune_key(dx, floor_log2(m), floor_log2(n), floor_log2(k)));
+    return it == g_tune.end() ? -1 : it->second;
+}
+
+void choose_class(Plan *pl, int64_t m, int64_t n, int64_t k) {
+    if (pl->form != HLB_FORM_INT8 || pl->np != 3) return;
+    int cls = g_force_class.load();
+    if (cls < 0) cls = tune_lookup(pl->nx, m, n, k);
+    if (cls < 0) {
+        // padding waste: rows padded to the tile height, columns to the tile width
+        const I8Shape a = i8_shape(pl->np, pl->nx, 0), b = i8_shape(pl->np, pl->nx, 1);
+        auto padded = [&](const I8Shape &sh) {
+            return (double)((m + sh.bm - 1) / sh.bm * sh.bm) * (double)((n + sh.bn - 1) / sh.bn * sh.bn);
+        };
+        cls = padded(b) < padded(a) ? 1 : 0;
+    }
+    const I8Shape sh = i8_shape(pl->np, pl->nx, cls);
+    if (!sh.dp) return;
+    pl->cls = cls;
+    pl->bm = sh.bm;
+    pl->bn = sh.bn;
 }
 
 void fill_seg(Seg &s, uint64_t q, int limb_bits) {
@@ -337,7 +399,7 @@ hlb_status run_products(const Plan &pl, const int64_t *P, int64_t ldp, int64_t m
         hipError_t e;
         if (pl.form == HLB_FORM_INT8) {
             ProfScope ps("gemm_i8", s);
-            e = launch_gemm_i8(pl.np, pl.nx, a, s);
+            e = launch_gemm_i8(pl.np, pl.nx, pl.cls, a, s);
         } else {
             ProfScope ps("gemm_f64", s);
             e = launch_gemm_f64(pl.np, pl.nx, a, s);
@@ -413,6 +475,7 @@ hlb_status hlb_mod_pp_mm(uint64_t q, int64_t m, int64_t k, int64_t n, const uint
     Plan pl;
     hlb_status st = plan(0, k, q, 0, form, &pl);
     if (st != HLB_OK) return st;
+    choose_class(&pl, m, n, k);
     int n_xcd = 8;
     if ((st = device_ready(&n_xcd)) != HLB_OK) return st;
     std::vector<OutSpec> outs{{C, X, ldc, ldx, n, q}};
@@ -444,6 +507,7 @@ hlb_status hlb_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t
     }
     Plan pl;
     if ((st = plan(1, k, qmax, std::max<int64_t>(p_absmax, 1), form, &pl)) != HLB_OK) return st;
+    choose_class(&pl, m, std::max(nA, nB), k);
     std::vector<OutSpec> outs;
     for (int l = 0; l < L; ++l) {
         if (nA > 0) outs.push_back({PA + (int64_t)l * m * nA, A + (int64_t)l * k * nA, nA, nA, nA, primes[l]});
@@ -500,6 +564,10 @@ hlb_status hlb_set_option(int option, int64_t value) {
         case HLB_OPT_BATCH_GRAPH:
             g_batch_graph.store(value ? 1 : 0);
             return HLB_OK;
+        case HLB_OPT_FORCE_CLASS:
+            if (value < -1 || value > 1) return HLB_EINVAL;
+            g_force_class.store((int)value);
+            return HLB_OK;
         default: return HLB_EUNSUP;
     }
 }
@@ -529,6 +597,35 @@ hlb_status hlb_profile_reset(void) {
     }
     g_prof.clear();
     return HLB_OK;
+}
+
+hlb_status hlb_tune_set(int x_digits, int log2m, int log2n, int log2k, int cls) {
+    if (x_digits < 1 || x_digits > 8 || log2m < 0 || log2m > 63 || log2n < 0 || log2n > 63 || log2k < 0 ||
+        log2k > 63 || cls < -1 || cls > 1)
+        return HLB_EINVAL;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    const uint32_t key = tune_key(x_digits, log2m, log2n, log2k);
+    if (cls < 0) g_tune.erase(key);
+    else g_tune[key] = cls;
+    return HLB_OK;
+}
+
+hlb_status hlb_tune_load(const char *path) {
+    if (!path) return HLB_EINVAL;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    return tune_load_locked(path);
+}
+
+int hlb_tune_class(int x_digits, int64_t m, int64_t n, int64_t k) {
+    if (m < 1 || n < 1 || k < 1) return -1;
+    Plan pl;
+    pl.form = HLB_FORM_INT8;
+    pl.np = 3;
+    pl.nx = x_digits;
+    const I8Shape sh = i8_shape(3, x_digits, 0);
+    if (!sh.dp) return -1;
+    choose_class(&pl, m, n, k);
+    return pl.cls;
 }
 
 hlb_status hlb_release(void) {

@@ -1,21 +1,386 @@
-// batch.cpp -- hlb_cp_mm_batch: many CP-MMs of uneven shapes over shared primes.
+// batch.hip -- hlb_cp_mm_batch: many CP-MMs of uneven shapes over shared RNS primes.
+//
+// Every CP-MM is two Mod-PP-MMs per prime (Theorem th:pcmm-shs), and the per-prime products
+// are independent (as in Section 6.1, Strategy 3), so a batch is one flat list of output
+// tiles.  INT8 form: one launch splits every plaintext, one launch splits every ciphertext
+// part, a tiny kernel zeroes the work counter, and one persistent launch (one workgroup per
+// CU) pulls tiles from the counter, largest K first.  Each problem uses the tile class the
+// planner picks for its shape.  The four launches are captured once per batch signature
+// into a HIP graph and replayed on later calls with the same signature.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
 #include "../../include/hlb.h"
+#include "common.hpp"
 #include "host.hpp"
+#include "launch.hpp"
 
 namespace hlb {
-void batch_release() {}
+
+namespace {
+
+struct BatchLayout {
+    int dp = 3, dx = 7;
+    bool fold = false;
+    int kfold = 0;
+    std::vector<SplitJob> pjobs, xjobs;
+    int64_t p_wgs = 0, x_wgs = 0;
+    std::vector<BatchProb> probs;
+    std::vector<BatchSeg> segs;
+    int64_t total_items = 0;
+    // workspace offsets (bytes) relative to the workspace base
+    size_t off_pjobs = 0, off_xjobs = 0, off_probs = 0, off_segs = 0, off_counter = 0, off_digits = 0;
+    size_t bytes = 0;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Builds descriptors for an INT8 batch.  Digit-buffer pointers are stored as offsets from
+// the start of the digit region and rebased by `rebase` once the workspace exists.
+hlb_status build_layout(const hlb_cpmm_problem *probs, int count, const uint64_t *primes, int L,
+                        BatchLayout &lay) {
+    uint64_t qmax = 0;
+    for (int l = 0; l < L; ++l) qmax = std::max(qmax, primes[l]);
+    Plan base;
+    hlb_status st = plan(1, 1, qmax, 1, HLB_FORM_INT8, &base);
+    if (st != HLB_OK) return st;
+    if (base.np != 3) return HLB_EUNSUP;
+    lay.dp = base.np;
+    lay.dx = base.nx;
+    lay.kfold = (int)std::max<int64_t>(1, base.kchunk / kBK8);
+
+    // problems in descending order of K blocks: longest tiles are handed out first
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].k > probs[b].k; });
+
+    size_t digit_off = 0;
+    for (int oi = 0; oi < count; ++oi) {
+        const hlb_cpmm_problem &p = probs[order[oi]];
+        if (p.m == 0 || p.k == 0 || (p.nA == 0 && p.nB == 0)) continue;
+        Plan pl = base;
+        choose_class(&pl, p.m, std::max(p.nA, p.nB), p.k);
+        const int64_t kblocks = (p.k + kBK8 - 1) / kBK8;
+        if (kblocks > lay.kfold) lay.fold = true;
+        const int64_t tiles_m = (p.m + pl.bm - 1) / pl.bm;
+        const int64_t p_tile = (int64_t)lay.dp * pl.bm * kBK8, x_tile = (int64_t)lay.dx * pl.bn * kBK8;
+
+        BatchProb bp;
+        std::memset(&bp, 0, sizeof(bp));
+        bp.item_start = lay.total_items;
+        bp.Pd = (const int8_t *)(uintptr_t)digit_off;
+        bp.m = p.m;
+        bp.kblocks = (int32_t)kblocks;
+        bp.tiles_m = (int32_t)tiles_m;
+        bp.cls = pl.cls;
+        bp.seg0 = (int32_t)lay.segs.size();
+
+        SplitJob pj;
+        std::memset(&pj, 0, sizeof(pj));
+        pj.wg_start = lay.p_wgs;
+        pj.P = p.P;
+        pj.ld = p.ldp;
+        pj.rows = p.m;
+        pj.k = p.k;
+        pj.kblocks = (int32_t)kblocks;
+        pj.R = pl.bm;
+        pj.rows_side = 1;
+        pj.out = (int8_t *)(uintptr_t)digit_off;
+        lay.pjobs.push_back(pj);
+        lay.p_wgs += tiles_m * kblocks;
+        digit_off += (size_t)(tiles_m * kblocks * p_tile);
+
+        bp.Xd = (const int8_t *)(uintptr_t)digit_off;
+        int32_t tb = 0;
+        for (int l = 0; l < L; ++l) {
+            for (int part = 0; part < 2; ++part) {
+                const int64_t n = part == 0 ? p.nA : p.nB;
+                if (n == 0) continue;
+                const uint64_t *X = (part == 0 ? p.A : p.B) + (int64_t)l * p.k * n;
+                uint64_t *C = (part == 0 ? p.PA : p.PB) + (int64_t)l * p.m * n;
+                const int64_t tiles = (n + pl.bn - 1) / pl.bn;
+                BatchSeg sg;
+                std::memset(&sg, 0, sizeof(sg));
+                sg.C = C;
+                sg.ldc = n;
+                sg.n = n;
+                sg.q = primes[l];
+                sg.qinv = 1.0 / (double)primes[l];
+                sg.tile_begin = tb;
+                lay.segs.push_back(sg);
+                SplitJob xj;
+                std::memset(&xj, 0, sizeof(xj));
+                xj.wg_start = lay.x_wgs;
+                xj.X = X;
+                xj.ld = n;
+                xj.cols = n;
+                xj.k = p.k;
+                xj.kblocks = (int32_t)kblocks;
+                xj.R = pl.bn;
+                xj.rows_side = 0;
+                xj.out = (int8_t *)(uintptr_t)(digit_off + (size_t)tb * kblocks * x_tile);
+                lay.xjobs.push_back(xj);
+                lay.x_wgs += tiles * kblocks;
+                tb += (int32_t)tiles;
+            }
+        }
+        bp.tiles_n = tb;
+        bp.nseg = (int32_t)lay.segs.size() - bp.seg0;
+        digit_off += (size_t)tb * kblocks * x_tile;
+        lay.total_items += tiles_m * tb;
+        lay.probs.push_back(bp);
+    }
+    if (lay.total_items > INT32_MAX || lay.p_wgs > INT32_MAX || lay.x_wgs > INT32_MAX) return HLB_EINVAL;
+    size_t off = 0;
+    lay.off_pjobs = off;
+    off = align_up(off + lay.pjobs.size() * sizeof(SplitJob), 256);
+    lay.off_xjobs = off;
+    off = align_up(off + lay.xjobs.size() * sizeof(SplitJob), 256);
+    lay.off_probs = off;
+    off = align_up(off + lay.probs.size() * sizeof(BatchProb), 256);
+    lay.off_segs = off;
+    off = align_up(off + lay.segs.size() * sizeof(BatchSeg), 256);
+    lay.off_counter = off;
+    off = align_up(off + 256, 256);
+    lay.off_digits = off;
+    lay.bytes = off + digit_off;
+    return HLB_OK;
+}
+
+// Turns digit offsets into device addresses inside a workspace at `base`.
+void rebase(BatchLayout &lay, char *base) {
+    char *digits = base + lay.off_digits;
+    for (SplitJob &j : lay.pjobs) j.out = (int8_t *)(digits + (uintptr_t)j.out);
+    for (SplitJob &j : lay.xjobs) j.out = (int8_t *)(digits + (uintptr_t)j.out);
+    for (BatchProb &p : lay.probs) {
+        p.Pd = (const int8_t *)(digits + (uintptr_t)p.Pd);
+        p.Xd = (const int8_t *)(digits + (uintptr_t)p.Xd);
+    }
+}
+
+// Host image of the descriptor region (everything before the digit buffers).
+std::vector<char> descriptor_image(const BatchLayout &lay) {
+    std::vector<char> img(lay.off_digits, 0);
+    std::memcpy(img.data() + lay.off_pjobs, lay.pjobs.data(), lay.pjobs.size() * sizeof(SplitJob));
+    std::memcpy(img.data() + lay.off_xjobs, lay.xjobs.data(), lay.xjobs.size() * sizeof(SplitJob));
+    std::memcpy(img.data() + lay.off_probs, lay.probs.data(), lay.probs.size() * sizeof(BatchProb));
+    std::memcpy(img.data() + lay.off_segs, lay.segs.data(), lay.segs.size() * sizeof(BatchSeg));
+    return img;
+}
+
+// The launch sequence of a batch on stream s (capturable: kernels only).
+hlb_status enqueue(const BatchLayout &lay, char *base, int grid, hipStream_t s) {
+    BatchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.probs = (const BatchProb *)(base + lay.off_probs);
+    a.segs = (const BatchSeg *)(base + lay.off_segs);
+    a.counter = (unsigned int *)(base + lay.off_counter);
+    a.total_items = lay.total_items;
+    a.nprob = (int32_t)lay.probs.size();
+    a.kfold = lay.fold ? lay.kfold : INT32_MAX;
+    a.group_m = 4;
+    {
+        ProfScope ps("split_p", s);
+        if (launch_split_batch_i8(lay.dp, (const SplitJob *)(base + lay.off_pjobs), (int)lay.pjobs.size(), lay.p_wgs,
+                                  s) != hipSuccess)
+            return HLB_EDEVICE;
+    }
+    {
+        ProfScope ps("split_x", s);
+        if (launch_split_batch_i8(lay.dx, (const SplitJob *)(base + lay.off_xjobs), (int)lay.xjobs.size(), lay.x_wgs,
+                                  s) != hipSuccess)
+            return HLB_EDEVICE;
+    }
+    if (launch_reset_counter(a.counter, s) != hipSuccess) return HLB_EDEVICE;
+    ProfScope ps("batch_i8", s);
+    if (launch_gemm_i8_batch(lay.dp, lay.dx, lay.fold, a, grid, s) != hipSuccess) return HLB_EDEVICE;
+    return HLB_OK;
+}
+
+// ------------------------------- graph cache -------------------------------------------
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    char *ws = nullptr;
+};
+std::mutex g_graph_mu;
+std::map<std::vector<uint64_t>, GraphEntry> g_graphs;
+constexpr size_t kMaxGraphs = 16;
+
+void destroy_entry(GraphEntry &e) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    if (e.ws) (void)hipFree(e.ws);
+    e = GraphEntry{};
+}
+
+// Everything the captured launches depend on: device, stream, every problem field, the
+// primes, and the plan (digit counts, fold chunk, tile class of every problem).
+std::vector<uint64_t> signature(const hlb_cpmm_problem *probs, int count, const uint64_t *primes, int L,
+                                int dev, hipStream_t s, const BatchLayout &lay) {
+    std::vector<uint64_t> sig;
+    sig.reserve((size_t)count * 11 + L + lay.probs.size() + 8);
+    sig.push_back((uint64_t)dev);
+    sig.push_back((uint64_t)(uintptr_t)s);
+    sig.push_back((uint64_t)lay.dp);
+    sig.push_back((uint64_t)lay.dx);
+    sig.push_back((uint64_t)(lay.fold ? lay.kfold : 0));
+    for (const BatchProb &p : lay.probs) sig.push_back((uint64_t)p.cls);
+    sig.push_back((uint64_t)L);
+    for (int l = 0; l < L; ++l) sig.push_back(primes[l]);
+    for (int i = 0; i < count; ++i) {
+        const hlb_cpmm_problem &p = probs[i];
+        const uint64_t f[] = {(uint64_t)p.m, (uint64_t)p.k, (uint64_t)p.nA, (uint64_t)p.nB, (uint64_t)(uintptr_t)p.P,
+                              (uint64_t)p.ldp, (uint64_t)p.p_absmax, (uint64_t)(uintptr_t)p.A,
+                              (uint64_t)(uintptr_t)p.B, (uint64_t)(uintptr_t)p.PA, (uint64_t)(uintptr_t)p.PB};
+        sig.insert(sig.end(), f, f + 11);
+    }
+    return sig;
+}
+
+int persistent_grid(const BatchLayout &lay) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    }
+    return (int)std::min<int64_t>(cus, lay.total_items);
+}
+
+}  // namespace
+
+void batch_release() {
+    std::lock_guard<std::mutex> g(g_graph_mu);
+    for (auto &kv : g_graphs) destroy_entry(kv.second);
+    g_graphs.clear();
+}
+
 }  // namespace hlb
+
+using namespace hlb;
 
 extern "C" hlb_status hlb_cp_mm_batch(const hlb_cpmm_problem *probs, int count, const uint64_t *primes, int L,
                                       int form, void *stream) {
-    if (count < 0 || (count > 0 && !probs)) return HLB_EINVAL;
+    if (count < 0 || (count > 0 && !probs) || L < 0 || L > 1024 || (L > 0 && !primes)) return HLB_EINVAL;
+    if (count == 0 || L == 0) return HLB_OK;
+    for (int l = 0; l < L; ++l)
+        if (check_modulus(primes[l]) != HLB_OK) return HLB_EINVAL;
+    // argument checks for every problem before any work is enqueued
     for (int i = 0; i < count; ++i) {
         const hlb_cpmm_problem &p = probs[i];
-        hlb_status st = hlb_cp_mm(p.m, p.k, p.nA, p.nB, p.P, p.ldp, p.p_absmax, p.A, p.B, primes, L, p.PA, p.PB,
-                                  form, stream);
-        if (st != HLB_OK) return st;
+        if (p.m < 0 || p.k < 0 || p.nA < 0 || p.nB < 0 || p.p_absmax < 0 || (uint64_t)p.p_absmax >= kMaxModulus)
+            return HLB_EINVAL;
+        if (p.m == 0 || (p.nA == 0 && p.nB == 0)) continue;
+        if ((p.nA > 0 && !p.PA) || (p.nB > 0 && !p.PB)) return HLB_EINVAL;
+        if (p.k > 0 && (!p.P || p.ldp < p.k || (p.nA > 0 && !p.A) || (p.nB > 0 && !p.B))) return HLB_EINVAL;
     }
-    return HLB_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hlb_status st = device_ready(nullptr);
+    if (st != HLB_OK) return st;
+
+    // The persistent INT8 path needs every plaintext within 3 digits; other batches (and the
+    // FP64 form) run problem by problem through hlb_cp_mm.
+    bool persistent = form == HLB_FORM_INT8 || form == HLB_FORM_AUTO;
+    std::vector<hlb_cpmm_problem> local(probs, probs + count);
+    for (hlb_cpmm_problem &p : local) {
+        if (p.m == 0 || p.k == 0 || (p.nA == 0 && p.nB == 0)) continue;
+        if (p.p_absmax == 0) {
+            int64_t mx = 0;
+            if ((st = hlb_plaintext_absmax(p.P, p.m, p.k, p.ldp, &mx, stream)) != HLB_OK) return st;
+            if ((uint64_t)mx >= kMaxModulus) return HLB_ERANGE;
+            p.p_absmax = std::max<int64_t>(mx, 1);
+        }
+        if (i8_digits_for((uint64_t)p.p_absmax) > 3) persistent = false;
+    }
+    uint64_t qmax = 0;
+    for (int l = 0; l < L; ++l) qmax = std::max(qmax, primes[l]);
+    if (i8_digits_for(qmax - 1) > 7) persistent = false;
+    if (!persistent) {
+        for (const hlb_cpmm_problem &p : local) {
+            st = hlb_cp_mm(p.m, p.k, p.nA, p.nB, p.P, p.ldp, p.p_absmax, p.A, p.B, primes, L, p.PA, p.PB, form, stream);
+            if (st != HLB_OK) return st;
+        }
+        return HLB_OK;
+    }
+    // k == 0 problems write zeros; they take no tiles
+    for (const hlb_cpmm_problem &p : local) {
+        if (p.k != 0 || p.m == 0) continue;
+        for (int l = 0; l < L; ++l) {
+            if (p.nA > 0 && hipMemsetAsync(p.PA + (int64_t)l * p.m * p.nA, 0, (size_t)(p.m * p.nA * 8), s) != hipSuccess)
+                return HLB_EDEVICE;
+            if (p.nB > 0 && hipMemsetAsync(p.PB + (int64_t)l * p.m * p.nB, 0, (size_t)(p.m * p.nB * 8), s) != hipSuccess)
+                return HLB_EDEVICE;
+        }
+    }
+
+    BatchLayout lay;
+    if ((st = build_layout(local.data(), count, primes, L, lay)) != HLB_OK) return st;
+    if (lay.total_items == 0) return HLB_OK;
+    const int grid = persistent_grid(lay);
+
+    if (!opt_batch_graph()) {
+        // eager: stream-ordered workspace, descriptors uploaded, four launches
+        void *ws = nullptr;
+        if ((st = ws_alloc(&ws, lay.bytes, s)) != HLB_OK) return st;
+        rebase(lay, (char *)ws);
+        std::vector<char> img = descriptor_image(lay);
+        if (hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, s) != hipSuccess) st = HLB_EDEVICE;
+        if (st == HLB_OK) st = enqueue(lay, (char *)ws, grid, s);
+        // the host image must outlive the copy
+        if (hipStreamSynchronize(s) != hipSuccess && st == HLB_OK) st = HLB_EDEVICE;
+        ws_free(ws, s);
+        return st;
+    }
+
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const std::vector<uint64_t> sig = signature(local.data(), count, primes, L, dev, s, lay);
+    std::lock_guard<std::mutex> g(g_graph_mu);
+    auto it = g_graphs.find(sig);
+    if (it == g_graphs.end()) {
+        if (g_graphs.size() >= kMaxGraphs) {
+            // keep the cache bounded: drop everything (entries are cheap to rebuild)
+            if (hipStreamSynchronize(s) != hipSuccess) return HLB_EDEVICE;
+            for (auto &kv : g_graphs) destroy_entry(kv.second);
+            g_graphs.clear();
+        }
+        GraphEntry e;
+        if (hipMalloc((void **)&e.ws, lay.bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return HLB_ENOMEM;
+        }
+        rebase(lay, e.ws);
+        std::vector<char> img = descriptor_image(lay);
+        if (hipMemcpy(e.ws, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            destroy_entry(e);
+            return HLB_EDEVICE;
+        }
+        hipStream_t cap = nullptr;
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+            destroy_entry(e);
+            return HLB_EDEVICE;
+        }
+        hlb_status cst = HLB_OK;
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) cst = HLB_EDEVICE;
+        if (cst == HLB_OK) {
+            cst = enqueue(lay, e.ws, grid, cap);
+            if (hipStreamEndCapture(cap, &e.graph) != hipSuccess && cst == HLB_OK) cst = HLB_EDEVICE;
+        }
+        (void)hipStreamDestroy(cap);
+        if (cst == HLB_OK && hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess)
+            cst = HLB_EDEVICE;
+        if (cst != HLB_OK) {
+            (void)hipGetLastError();
+            destroy_entry(e);
+            return cst;
+        }
+        it = g_graphs.emplace(sig, e).first;
+    }
+    return hipGraphLaunch(it->second.exec, s) == hipSuccess ? HLB_OK : HLB_EDEVICE;
 }

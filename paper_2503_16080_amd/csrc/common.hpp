@@ -123,6 +123,42 @@ struct GemmArgs {
     Seg seg[kMaxSegs];
 };
 
+// One job of a batched digit split: a whole matrix of one problem, split into the tile-major
+// workspace; the job owns workgroups [wg_start, wg_start + tiles * kblocks).
+struct SplitJob {
+    int64_t wg_start;
+    const int64_t *P;   // plaintext side (rows_side = 1): rows x k, row stride ld
+    const uint64_t *X;  // ciphertext side (rows_side = 0): k x cols, row stride ld
+    int64_t ld, rows, cols, k;
+    int32_t kblocks, R, rows_side, pad;
+    int8_t *out;
+};
+
+// A problem of a batch: its digit workspaces, tiles and output segments (seg0 .. seg0+nseg).
+struct BatchProb {
+    int64_t item_start;  // first work item (tile) of the problem in the batch's work list
+    const int8_t *Pd;
+    const int8_t *Xd;
+    int64_t m;
+    int32_t kblocks, tiles_m, tiles_n, cls, seg0, nseg;
+};
+
+struct BatchSeg {
+    uint64_t *C;
+    int64_t ldc, n;
+    uint64_t q;
+    double qinv;
+    int32_t tile_begin, pad;
+};
+
+struct BatchArgs {
+    const BatchProb *probs;
+    const BatchSeg *segs;
+    unsigned int *counter;  // next work item; zeroed by a reset kernel before each launch
+    int64_t total_items;
+    int32_t nprob, kfold, group_m, pad;
+};
+
 // Maps a workgroup id to (row tile, column tile).  Workgroups are dealt to the XCDs
 // round-robin, so ids w, w+n_xcd, ... share an XCD and its L2.  The remap gives every XCD a
 // contiguous run of logical tiles, and the raster walks group_m row tiles column by column

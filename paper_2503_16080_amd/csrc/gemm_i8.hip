@@ -9,6 +9,9 @@
 // Exactness: a shift collects at most `pairs` digit products of magnitude <= 128*128 per K
 // element, so |c_s| <= pairs * kchunk * 2^14 < 2^31 for the K chunk the host plans; longer
 // K is cut into chunks whose partial results are folded into a 64-bit residue.
+//
+// Contents: digit-split kernels (single problem and batched), the per-tile GEMM body, the
+// grid kernel of one CP-MM / Mod-PP-MM, and the persistent kernel of a batch.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -27,6 +30,7 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // Entries outside the valid m x k (or k x n) range become zero digits.
 // ---------------------------------------------------------------------------------------
 constexpr int kSplitRowPad = 68;  // LDS row stride in bytes: 64 + 4 keeps dword writes conflict-free
+constexpr int kSplitLds = 7 * 128 * kSplitRowPad;
 
 template <int D>
 __device__ __forceinline__ void digits4(const uint64_t (&x)[4], uint32_t (&out)[D]) {
@@ -64,13 +68,11 @@ __device__ __forceinline__ void split_stage2(const uint8_t *lds, int8_t *tile_ou
     }
 }
 
-// Plaintext side: P is m x k row-major (signed int64 or residues), tile rows are rows of P.
+// One (row tile rb, k block kb) of the plaintext side: rows of P (signed int64 or residues).
 template <int D, int R>
-__global__ __launch_bounds__(kThreads) void split_rows_i8(const int64_t *__restrict__ P, int64_t ldp,
-                                                          int64_t m, int64_t k, int kblocks,
-                                                          int8_t *__restrict__ out) {
-    __shared__ uint8_t lds[D * R * kSplitRowPad];
-    const int rb = blockIdx.x / kblocks, kb = blockIdx.x % kblocks;
+__device__ __forceinline__ void split_rows_tile(const int64_t *__restrict__ P, int64_t ldp, int64_t m,
+                                                int64_t k, int kblocks, int rb, int kb, int8_t *out,
+                                                uint8_t *lds) {
     const int t = threadIdx.x;
     const int quad = t & 15;  // 4 consecutive K elements
 #pragma unroll 1
@@ -79,8 +81,7 @@ __global__ __launch_bounds__(kThreads) void split_rows_i8(const int64_t *__restr
         const int64_t k0 = (int64_t)kb * kBK8 + quad * 4;
         uint64_t x[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            x[e] = (row < m && k0 + e < k) ? (uint64_t)P[row * ldp + k0 + e] : 0;
+        for (int e = 0; e < 4; ++e) x[e] = (row < m && k0 + e < k) ? (uint64_t)P[row * ldp + k0 + e] : 0;
         uint32_t d[D];
         digits4<D>(x, d);
 #pragma unroll
@@ -90,19 +91,16 @@ __global__ __launch_bounds__(kThreads) void split_rows_i8(const int64_t *__restr
     split_stage2<D, R>(lds, out + ((int64_t)rb * kblocks + kb) * (D * R * kBK8));
 }
 
-// Ciphertext side: X is k x n row-major residues, tile rows are columns of X (transposed).
+// One (column tile cb, k block kb) of the ciphertext side: columns of X (transposed).
 template <int D, int R>
-__global__ __launch_bounds__(kThreads) void split_cols_i8(const uint64_t *__restrict__ X, int64_t ldx,
-                                                          int64_t k, int64_t n, int kblocks,
-                                                          int8_t *__restrict__ out) {
-    __shared__ uint8_t lds[D * R * kSplitRowPad];
-    const int cb = blockIdx.x / kblocks, kb = blockIdx.x % kblocks;
+__device__ __forceinline__ void split_cols_tile(const uint64_t *__restrict__ X, int64_t ldx, int64_t k,
+                                                int64_t n, int kblocks, int cb, int kb, int8_t *out,
+                                                uint8_t *lds) {
     const int t = threadIdx.x;
-    constexpr int lanes_per_row = R;              // one column per lane
-    constexpr int quads_in_flight = kThreads / R; // K quads handled per pass
+    constexpr int quads_in_flight = kThreads / R;  // K quads handled per pass, one column per lane
 #pragma unroll 1
-    for (int qd = t / lanes_per_row; qd < 16; qd += quads_in_flight) {
-        const int c = t % lanes_per_row;
+    for (int qd = t / R; qd < 16; qd += quads_in_flight) {
+        const int c = t % R;
         const int64_t col = (int64_t)cb * R + c;
         const int64_t k0 = (int64_t)kb * kBK8 + qd * 4;
         uint64_t x[4];
@@ -117,14 +115,53 @@ __global__ __launch_bounds__(kThreads) void split_cols_i8(const uint64_t *__rest
     split_stage2<D, R>(lds, out + ((int64_t)cb * kblocks + kb) * (D * R * kBK8));
 }
 
+template <int D, int R>
+__global__ __launch_bounds__(kThreads) void split_rows_i8(const int64_t *__restrict__ P, int64_t ldp,
+                                                          int64_t m, int64_t k, int kblocks,
+                                                          int8_t *__restrict__ out) {
+    __shared__ uint8_t lds[D * R * kSplitRowPad];
+    split_rows_tile<D, R>(P, ldp, m, k, kblocks, blockIdx.x / kblocks, blockIdx.x % kblocks, out, lds);
+}
+
+template <int D, int R>
+__global__ __launch_bounds__(kThreads) void split_cols_i8(const uint64_t *__restrict__ X, int64_t ldx,
+                                                          int64_t k, int64_t n, int kblocks,
+                                                          int8_t *__restrict__ out) {
+    __shared__ uint8_t lds[D * R * kSplitRowPad];
+    split_cols_tile<D, R>(X, ldx, k, n, kblocks, blockIdx.x / kblocks, blockIdx.x % kblocks, out, lds);
+}
+
+// Batched splits: one launch covers every job of a batch; workgroup w finds its job by
+// binary search over the jobs' first workgroup indices.
+template <int D>
+__global__ __launch_bounds__(kThreads) void split_batch_i8(const SplitJob *__restrict__ jobs, int njobs) {
+    __shared__ uint8_t lds[kSplitLds];
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].wg_start <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    const int ji = lo;
+    const SplitJob &j = jobs[ji];
+    const int64_t local = w - j.wg_start;
+    const int tile = (int)(local / j.kblocks), kb = (int)(local % j.kblocks);
+    if (j.rows_side) {
+        if (j.R == 128) split_rows_tile<D, 128>(j.P, j.ld, j.rows, j.k, j.kblocks, tile, kb, j.out, lds);
+        else split_rows_tile<D, 64>(j.P, j.ld, j.rows, j.k, j.kblocks, tile, kb, j.out, lds);
+    } else {
+        if (j.R == 128) split_cols_tile<D, 128>(j.X, j.ld, j.k, j.cols, j.kblocks, tile, kb, j.out, lds);
+        else split_cols_tile<D, 64>(j.X, j.ld, j.k, j.cols, j.kblocks, tile, kb, j.out, lds);
+    }
+}
+
 // ---------------------------------------------------------------------------------------
-// Limb GEMM with fused recombination and mod-q epilogue.
+// Limb GEMM tile.
 //   A workgroup of WAVES_M x WAVES_N waves computes a BM x BN output tile (BM = 32*WAVES_M,
 //   BN = 32*WAVES_N); each wave owns one 32 x 32 block with NS int32 accumulators per output
 //   (one per shift), i.e. 16*NS accumulator registers per lane.  K advances 64 bytes per LDS
-//   stage (two MFMA K steps of 32), double-buffered: the next stage streams from global
-//   memory straight into the other LDS buffer while the current stage's MFMAs run, with
-//   one barrier per stage.
+//   stage (two MFMA K steps of 32).
 // ---------------------------------------------------------------------------------------
 template <int DP_, int DX_, int WAVES_M_, int WAVES_N_>
 struct I8Tile {
@@ -137,7 +174,14 @@ struct I8Tile {
     static constexpr int STAGE = P_TILE + X_TILE;
     static constexpr int P_CHUNKS = P_TILE / 16, X_CHUNKS = X_TILE / 16;
     static_assert(P_CHUNKS % 64 == 0 && X_CHUNKS % 64 == 0, "tiles are whole wave loads");
+    // Three LDS stages when they fit: global loads then have two stages of compute to land.
+    static constexpr int NBUF = 3 * STAGE <= 160 * 1024 ? 3 : 2;
+    static constexpr int LDS = NBUF * STAGE;
 };
+
+// Tile classes (8 waves each): class 0 = 128 x 64 outputs, class 1 = 64 x 128 outputs.
+template <int DP, int DX> using Class0 = I8Tile<DP, DX, 4, 2>;
+template <int DP, int DX> using Class1 = I8Tile<DP, DX, 2, 4>;
 
 // Exact integer value sum_s acc[s] 256^s reduced mod q, by Horner from the top shift:
 // r <- (256 r + c_s) mod q with r < q < 2^52 and |c_s| < 2^31, so every intermediate fits
@@ -150,7 +194,7 @@ __device__ __forceinline__ uint64_t recombine_i8(const int (&c)[NS], uint64_t q,
     return r;
 }
 
-// Copies `chunks` 16-byte chunks from global memory to LDS with the gfx950 direct-to-LDS
+// Copies CHUNKS 16-byte chunks from global memory to LDS with the gfx950 direct-to-LDS
 // load: lane l of a wave writes its 16 bytes at (wave-uniform LDS base) + 16 l, so the
 // linear chunk order of the tile-major workspace arrives unchanged and no staging
 // registers are used.  Chunks are dealt to waves in runs of 64.
@@ -198,8 +242,6 @@ __device__ __forceinline__ int loads_of_wave(int wave_u) {
     return n;
 }
 
-constexpr int kLdsBytes = 160 * 1024;
-
 // Workgroup barrier WITHOUT the memory fence of __syncthreads(): that fence waits for every
 // outstanding global load (vmcnt(0)), which would also wait for the direct-to-LDS loads of
 // the stages still in flight.  Visibility is handled explicitly instead: each wave waits
@@ -211,31 +253,34 @@ __device__ __forceinline__ void stage_barrier() {
     asm volatile("" ::: "memory");
 }
 
-template <class T, bool FOLD>
-__global__ __launch_bounds__(T::THREADS, 1) void gemm_i8_kernel(const GemmArgs args) {
-    // Three LDS stages when they fit: global loads then have two stages of compute to land
-    // instead of one.
-    constexpr int NBUF = 3 * T::STAGE <= kLdsBytes ? 3 : 2;
-    __shared__ __attribute__((aligned(16))) int8_t lds[NBUF * T::STAGE];
+// Everything one output tile needs.
+struct TileJob {
+    const int8_t *gP;  // first K block of this tile row's plaintext digits
+    const int8_t *gX;  // first K block of this tile column's ciphertext digits
+    int KB;            // K blocks
+    int kfold;         // K blocks accumulated before a fold
+    int64_t row0, m;   // first output row of the tile, valid rows of the problem
+    int64_t col0, n;   // first output column (within its segment), valid columns
+    uint64_t *C;
+    int64_t ldc;
+    uint64_t q;
+    double qinv;
+};
 
+// One output tile: K loop with the LDS pipeline, then the fused recombination / mod-q
+// epilogue.  On return no LDS access of this tile is outstanding.
+template <class T, bool FOLD>
+__device__ __forceinline__ void run_tile(const TileJob &job, int8_t *lds) {
+    constexpr int NBUF = T::NBUF;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave_u / T::WAVES_N, wn = wave_u % T::WAVES_N;
-    const int total = args.tiles_m * args.tiles_n;
-    int rb, cb;
-    map_tile(blockIdx.x, total, args.n_xcd, args.tiles_m, args.tiles_n, args.group_m, rb, cb);
-
-    const int8_t *gP = args.Pd + (int64_t)rb * args.kblocks * T::P_TILE;
-    const int8_t *gX = args.Xd + (int64_t)cb * args.kblocks * T::X_TILE;
+    const uint64_t q = job.q;
+    const double qinv = job.qinv;
 
     v16i acc[T::NS];
 #pragma unroll
     for (int s = 0; s < T::NS; ++s) acc[s] = v16i{0};
-
-    const int si = find_seg(args, cb);
-    const uint64_t q = args.seg[si].q;
-    const double qinv = args.seg[si].qinv;
-
     // running residues of folded K chunks (only materialised when FOLD)
     uint64_t part[FOLD ? 16 : 1];
     if constexpr (FOLD) {
@@ -245,8 +290,8 @@ __global__ __launch_bounds__(T::THREADS, 1) void gemm_i8_kernel(const GemmArgs a
 
     auto gload = [&](int kb, int buf) {
         int8_t *dp = lds + buf * T::STAGE;
-        copy_to_lds<T::THREADS, T::P_CHUNKS>(gP + (int64_t)kb * T::P_TILE, dp, tid, wave_u);
-        copy_to_lds<T::THREADS, T::X_CHUNKS>(gX + (int64_t)kb * T::X_TILE, dp + T::P_TILE, tid, wave_u);
+        copy_to_lds<T::THREADS, T::P_CHUNKS>(job.gP + (int64_t)kb * T::P_TILE, dp, tid, wave_u);
+        copy_to_lds<T::THREADS, T::X_CHUNKS>(job.gX + (int64_t)kb * T::X_TILE, dp + T::P_TILE, tid, wave_u);
     };
     const int loads_per_stage = loads_of_wave<T::THREADS, T::P_CHUNKS>(wave_u) +
                                 loads_of_wave<T::THREADS, T::X_CHUNKS>(wave_u);
@@ -256,7 +301,7 @@ __global__ __launch_bounds__(T::THREADS, 1) void gemm_i8_kernel(const GemmArgs a
     const int xcol = wn * 32 + (lane & 31);
     // One K half (32 bytes) of a stage: the DP plaintext and DX ciphertext fragments of this
     // lane, then the DP x DX digit-pair MFMAs into the shift accumulators.
-    using Frags = struct {
+    struct Frags {
         v4i a[T::DP];
         v4i b[T::DX];
     };
@@ -297,7 +342,7 @@ __global__ __launch_bounds__(T::THREADS, 1) void gemm_i8_kernel(const GemmArgs a
     // so every LDS read overlaps a half stage of MFMAs, and every stage's global loads have
     // NBUF-1 stages of compute to land.  At the barrier all waves have finished reading the
     // buffer of stage kb (hence it can be refilled) and have seen stage kb+1 land.
-    const int KB = args.kblocks;
+    const int KB = job.KB;
     // loads still allowed in flight when stage `need` must have landed, given that stages
     // up to min(KB-1, issued_hi) have been issued
     auto outstanding = [&](int need, int issued_hi) {
@@ -324,14 +369,13 @@ __global__ __launch_bounds__(T::THREADS, 1) void gemm_i8_kernel(const GemmArgs a
         if (kb + 1 < KB) read_frags(f0, (kb + 1) % NBUF, 0);
         mfmas(f1);
         if constexpr (FOLD) {
-            if ((kb + 1) % args.kfold == 0 && kb + 1 < KB) fold();
+            if ((kb + 1) % job.kfold == 0 && kb + 1 < KB) fold();
         }
     }
 
     // Epilogue: recombine, reduce, write canonical residues (row- and column-masked).
-    const Seg &sg = args.seg[si];
-    const int64_t row0 = (int64_t)rb * T::BM + wm * 32;
-    const int64_t col = (int64_t)(cb - sg.tile_begin) * T::BN + wn * 32 + (lane & 31);
+    const int64_t row0 = job.row0 + wm * 32;
+    const int64_t col = job.col0 + wn * 32 + (lane & 31);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         // 32x32 accumulator layout: column = lane % 32, row = 8 (r / 4) + 4 (lane / 32) + r % 4
@@ -341,8 +385,102 @@ __global__ __launch_bounds__(T::THREADS, 1) void gemm_i8_kernel(const GemmArgs a
         for (int s = 0; s < T::NS; ++s) c[s] = acc[s][r];
         uint64_t v = recombine_i8<T::NS>(c, q, qinv);
         if constexpr (FOLD) v = addmod(v, part[r], q);
-        if (row < args.m && col < sg.n) sg.C[row * sg.ldc + col] = v;
+        if (row < job.m && col < job.n) job.C[row * job.ldc + col] = v;
     }
+}
+
+// ---------------------------------------------------------------------------------------
+// Grid kernel of one problem: one workgroup per output tile (XCD-aware raster).
+// ---------------------------------------------------------------------------------------
+template <class T, bool FOLD>
+__global__ __launch_bounds__(T::THREADS, 1) void gemm_i8_kernel(const GemmArgs args) {
+    __shared__ __attribute__((aligned(16))) int8_t lds[T::LDS];
+    const int total = args.tiles_m * args.tiles_n;
+    int rb, cb;
+    map_tile(blockIdx.x, total, args.n_xcd, args.tiles_m, args.tiles_n, args.group_m, rb, cb);
+    const int si = find_seg(args, cb);
+    const Seg &sg = args.seg[si];
+    TileJob job;
+    job.gP = args.Pd + (int64_t)rb * args.kblocks * T::P_TILE;
+    job.gX = args.Xd + (int64_t)cb * args.kblocks * T::X_TILE;
+    job.KB = args.kblocks;
+    job.kfold = args.kfold;
+    job.row0 = (int64_t)rb * T::BM;
+    job.m = args.m;
+    job.col0 = (int64_t)(cb - sg.tile_begin) * T::BN;
+    job.n = sg.n;
+    job.C = sg.C;
+    job.ldc = sg.ldc;
+    job.q = sg.q;
+    job.qinv = sg.qinv;
+    run_tile<T, FOLD>(job, lds);
+}
+
+// ---------------------------------------------------------------------------------------
+// Persistent batch kernel: a fixed grid of workgroups pulls output tiles from one atomic
+// counter.  Work items are ordered by the host (largest K first); each item maps to a
+// problem by binary search over the problems' first work-item indices, then to a tile of
+// that problem in its own tile class.  Every workgroup exits when the counter passes the
+// end of the list.
+// ---------------------------------------------------------------------------------------
+template <int DP, int DX, bool FOLD>
+__global__ __launch_bounds__(256 * 2, 1) void gemm_i8_batch_kernel(const BatchArgs args) {
+    constexpr int L0 = Class0<DP, DX>::LDS, L1 = Class1<DP, DX>::LDS;
+    __shared__ __attribute__((aligned(16))) int8_t lds[L0 > L1 ? L0 : L1];
+    __shared__ int64_t item;
+    for (;;) {
+        if (threadIdx.x == 0) item = (int64_t)atomicAdd(args.counter, 1u);
+        __syncthreads();
+        const int64_t t = item;
+        __syncthreads();  // everyone has read `item` before thread 0 overwrites it
+        if (t >= args.total_items) return;
+        int lo = 0, hi = args.nprob - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (args.probs[mid].item_start <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchProb &p = args.probs[lo];
+        const int local = (int)(t - p.item_start);
+        // raster inside the problem: group_m row tiles walked column by column
+        const int span = args.group_m * p.tiles_n;
+        const int g = local / span, first = g * args.group_m;
+        const int gm = min(args.group_m, p.tiles_m - first);
+        const int in = local - g * span;
+        const int rb = first + in % gm, cb = in / gm;
+        int s = p.seg0;
+        for (int i = p.seg0 + 1; i < p.seg0 + p.nseg; ++i)
+            if (cb >= args.segs[i].tile_begin) s = i;
+        const BatchSeg &sg = args.segs[s];
+        TileJob job;
+        job.KB = p.kblocks;
+        job.kfold = args.kfold;
+        job.m = p.m;
+        job.n = sg.n;
+        job.C = sg.C;
+        job.ldc = sg.ldc;
+        job.q = sg.q;
+        job.qinv = sg.qinv;
+        if (p.cls == 0) {
+            using T = Class0<DP, DX>;
+            job.gP = p.Pd + (int64_t)rb * p.kblocks * T::P_TILE;
+            job.gX = p.Xd + (int64_t)cb * p.kblocks * T::X_TILE;
+            job.row0 = (int64_t)rb * T::BM;
+            job.col0 = (int64_t)(cb - sg.tile_begin) * T::BN;
+            run_tile<T, FOLD>(job, lds);
+        } else {
+            using T = Class1<DP, DX>;
+            job.gP = p.Pd + (int64_t)rb * p.kblocks * T::P_TILE;
+            job.gX = p.Xd + (int64_t)cb * p.kblocks * T::X_TILE;
+            job.row0 = (int64_t)rb * T::BM;
+            job.col0 = (int64_t)(cb - sg.tile_begin) * T::BN;
+            run_tile<T, FOLD>(job, lds);
+        }
+    }
+}
+
+__global__ void reset_counter_kernel(unsigned int *counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -368,6 +506,7 @@ hipError_t launch_split_rows_i8(int D, int R, const int64_t *P, int64_t ldp, int
                                 int tiles, int kblocks, int8_t *out, hipStream_t s) {
     if (tiles <= 0 || kblocks <= 0) return hipSuccess;
     if (R == 128 && D == 3) return launch_split_rows_t<3, 128>(P, ldp, m, k, tiles, kblocks, out, s);
+    if (R == 64 && D == 3) return launch_split_rows_t<3, 64>(P, ldp, m, k, tiles, kblocks, out, s);
     if (R == 64 && D == 7) return launch_split_rows_t<7, 64>(P, ldp, m, k, tiles, kblocks, out, s);
     return hipErrorInvalidValue;
 }
@@ -377,7 +516,19 @@ hipError_t launch_split_cols_i8(int D, int R, const uint64_t *X, int64_t ldx, in
     if (tiles <= 0 || kblocks <= 0) return hipSuccess;
     if (R == 64 && D == 7) return launch_split_cols_t<7, 64>(X, ldx, k, n, tiles, kblocks, out, s);
     if (R == 64 && D == 6) return launch_split_cols_t<6, 64>(X, ldx, k, n, tiles, kblocks, out, s);
+    if (R == 128 && D == 7) return launch_split_cols_t<7, 128>(X, ldx, k, n, tiles, kblocks, out, s);
+    if (R == 128 && D == 6) return launch_split_cols_t<6, 128>(X, ldx, k, n, tiles, kblocks, out, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_split_batch_i8(int D, const SplitJob *jobs, int njobs, int64_t total_wgs, hipStream_t s) {
+    if (njobs <= 0 || total_wgs <= 0) return hipSuccess;
+    if (total_wgs > INT32_MAX) return hipErrorInvalidValue;
+    if (D == 3) hipLaunchKernelGGL(split_batch_i8<3>, dim3((unsigned)total_wgs), dim3(kThreads), 0, s, jobs, njobs);
+    else if (D == 6) hipLaunchKernelGGL(split_batch_i8<6>, dim3((unsigned)total_wgs), dim3(kThreads), 0, s, jobs, njobs);
+    else if (D == 7) hipLaunchKernelGGL(split_batch_i8<7>, dim3((unsigned)total_wgs), dim3(kThreads), 0, s, jobs, njobs);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 template <class T, bool FOLD>
@@ -393,17 +544,35 @@ static hipError_t launch_gemm_fold(const GemmArgs &a, hipStream_t s) {
     return a.kfold < a.kblocks ? launch_gemm_t<T, true>(a, s) : launch_gemm_t<T, false>(a, s);
 }
 
-I8Shape i8_shape(int dp, int dx) {
-    if (dp == 3 && dx == 7) return {3, 7, 128, 64};
-    if (dp == 3 && dx == 6) return {3, 6, 128, 64};
+I8Shape i8_shape(int dp, int dx, int cls) {
+    if (dp == 3 && (dx == 7 || dx == 6)) return cls == 1 ? I8Shape{3, dx, 64, 128} : I8Shape{3, dx, 128, 64};
     if (dp == 7 && dx == 7) return {7, 7, 64, 64};
     return {0, 0, 0, 0};
 }
 
-hipError_t launch_gemm_i8(int dp, int dx, const GemmArgs &a, hipStream_t s) {
-    if (dp == 3 && dx == 7) return launch_gemm_fold<I8Tile<3, 7, 4, 2>>(a, s);
-    if (dp == 3 && dx == 6) return launch_gemm_fold<I8Tile<3, 6, 4, 2>>(a, s);
+hipError_t launch_gemm_i8(int dp, int dx, int cls, const GemmArgs &a, hipStream_t s) {
+    if (dp == 3 && dx == 7) return cls == 1 ? launch_gemm_fold<Class1<3, 7>>(a, s) : launch_gemm_fold<Class0<3, 7>>(a, s);
+    if (dp == 3 && dx == 6) return cls == 1 ? launch_gemm_fold<Class1<3, 6>>(a, s) : launch_gemm_fold<Class0<3, 6>>(a, s);
     if (dp == 7 && dx == 7) return launch_gemm_fold<I8Tile<7, 7, 2, 2>>(a, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reset_counter(unsigned int *counter, hipStream_t s) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_i8_batch(int dp, int dx, bool fold, const BatchArgs &a, int grid, hipStream_t s) {
+    if (grid <= 0 || a.total_items <= 0) return hipSuccess;
+#define HLB_BATCH(DP_, DX_)                                                                         \
+    if (dp == DP_ && dx == DX_) {                                                                   \
+        if (fold) hipLaunchKernelGGL((gemm_i8_batch_kernel<DP_, DX_, true>), dim3(grid), dim3(512), 0, s, a);  \
+        else hipLaunchKernelGGL((gemm_i8_batch_kernel<DP_, DX_, false>), dim3(grid), dim3(512), 0, s, a);      \
+        return hipGetLastError();                                                                   \
+    }
+    HLB_BATCH(3, 7)
+    HLB_BATCH(3, 6)
+#undef HLB_BATCH
     return hipErrorInvalidValue;
 }
 

@@ -21,10 +21,15 @@ struct Plan {
     int pairs = 0;          // most limb products sharing one accumulator
     int64_t kchunk = 0;     // K elements accumulated before a fold
     int bm = 0, bn = 0, bk = 0;
+    int cls = 0;            // INT8 tile class (0: 128 x 64, 1: 64 x 128)
     double acc_bound_log2 = 0.0;
 };
 
 hlb_status plan(int kind, int64_t k, uint64_t qmax, int64_t pmax, int form, Plan *pl);
+// Picks the INT8 tile class of a problem (m rows, n columns per output matrix, depth k) and
+// updates pl->cls / bm / bn accordingly; no-op for plans with a single class.
+void choose_class(Plan *pl, int64_t m, int64_t n, int64_t k);
+int i8_digits_for(uint64_t vmax);
 hlb_status check_modulus(uint64_t q);
 hlb_status device_ready(int *n_xcd);
 void fill_seg(Seg &s, uint64_t q, int limb_bits);

@@ -13,7 +13,8 @@ struct I8Shape {
     int dp, dx;  // 0 when no instantiation exists
     int bm, bn;
 };
-I8Shape i8_shape(int dp, int dx);
+// cls: tile class (0 = 128 x 64 outputs, 1 = 64 x 128 outputs) where the digits allow both.
+I8Shape i8_shape(int dp, int dx, int cls);
 
 // Digit split of the left operand (rows of P) into the tile-major workspace.
 hipError_t launch_split_rows_i8(int D, int R, const int64_t *P, int64_t ldp, int64_t m, int64_t k,
@@ -21,7 +22,12 @@ hipError_t launch_split_rows_i8(int D, int R, const int64_t *P, int64_t ldp, int
 // Digit split of the right operand (columns of X, transposed) into the workspace.
 hipError_t launch_split_cols_i8(int D, int R, const uint64_t *X, int64_t ldx, int64_t k, int64_t n,
                                 int tiles, int kblocks, int8_t *out, hipStream_t s);
-hipError_t launch_gemm_i8(int dp, int dx, const GemmArgs &a, hipStream_t s);
+hipError_t launch_gemm_i8(int dp, int dx, int cls, const GemmArgs &a, hipStream_t s);
+// Batch path: all splits of a batch in one launch, the work counter reset, and the
+// persistent GEMM over every tile of every problem.
+hipError_t launch_split_batch_i8(int D, const SplitJob *jobs, int njobs, int64_t total_wgs, hipStream_t s);
+hipError_t launch_reset_counter(unsigned int *counter, hipStream_t s);
+hipError_t launch_gemm_i8_batch(int dp, int dx, bool fold, const BatchArgs &a, int grid, hipStream_t s);
 
 // FP64 form: limb counts of each operand; returns false when no instantiation exists.
 bool f64_supported(int np, int nx);

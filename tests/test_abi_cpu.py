@@ -137,3 +137,38 @@ def test_no_silent_fallback_without_library(monkeypatch):
     monkeypatch.setattr(hlb, "_LIB_PATH", "/nonexistent/libhlb.so")
     with pytest.raises(hlb.HlbError):
         hlb.load()
+
+
+def test_tile_class_heuristic_and_tuning_table(tmp_path):
+    # padding-waste heuristic: 64-row problems take the 64 x 128 class, square ones 128 x 64
+    assert hlb.hlb_tune_class(7, 64, 1024, 1024) == 1
+    assert hlb.hlb_tune_class(7, 8192, 8192, 8192) == 0
+    assert hlb.hlb_tune_class(6, 60, 4096, 512) == 1    # pads to 64 rows instead of 128
+    assert hlb.hlb_tune_class(6, 100, 4096, 512) == 0   # both classes pad to 128 rows
+    # table entries override the heuristic for their bucket only
+    hlb.hlb_tune_set(7, 13, 13, 13, 1)
+    try:
+        assert hlb.hlb_tune_class(7, 8192, 8192, 8192) == 1
+        assert hlb.hlb_tune_class(7, 8192, 8192, 4096) == 0
+    finally:
+        hlb.hlb_tune_set(7, 13, 13, 13, -1)
+    assert hlb.hlb_tune_class(7, 8192, 8192, 8192) == 0
+    f = tmp_path / "tune.txt"
+    f.write_text("# comment\n6 6 10 10 0\nnot a line\n")
+    hlb.hlb_tune_load(str(f))
+    try:
+        assert hlb.hlb_tune_class(6, 64, 1024, 1024) == 0
+    finally:
+        hlb.hlb_tune_set(6, 6, 10, 10, -1)
+    assert hlb.hlb_tune_class(6, 64, 1024, 1024) == 1
+    with pytest.raises(hlb.HlbError):
+        hlb.hlb_tune_set(7, 1, 1, 1, 5)
+    with pytest.raises(hlb.HlbError):
+        hlb.hlb_tune_load(str(tmp_path / "missing.txt"))
+    try:
+        hlb.set_option(hlb.OPT_FORCE_CLASS, 0)
+        assert hlb.hlb_tune_class(7, 64, 1024, 1024) == 0
+    finally:
+        hlb.set_option(hlb.OPT_FORCE_CLASS, -1)
+    with pytest.raises(hlb.HlbError):
+        hlb.set_option(hlb.OPT_FORCE_CLASS, 2)
