@@ -43,10 +43,68 @@ def _parse():
     ap.add_argument("--workload", choices=["cpmm", "batch"], default="cpmm",
                     help="cpmm: one CP-MM of size --d (default); batch: 64 CP-MMs of uneven "
                          "shapes over 4 primes of 45 bits")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the counter summary from two rocprofv3 --pmc output directories "
+                         "(FETCH_SIZE run, WRITE_SIZE run) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run 3 device-to-device copies of 1 GiB (a reference kernel of "
                          "known traffic for scaling hardware byte counters)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_i8_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2503_16080_amd", "csrc", f) for f in ("gemm_i8.hip", "common.hpp")]
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the INT8 limb-GEMM sources: counter data is valid only for this hash."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(d, L):
+    """HBM bytes per limb-GEMM launch from the committed counter summary, or None when the
+    summary is missing, is for another workload, or predates the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash() or t.get("d") != d or t.get("primes") != L:
+        return None
+    return t["fetch_kib"] * 1024 * t["fetch_scale"] + t["write_kib"] * 1024 * t["write_scale"]
+
+
+def summarize_counters(fetch_dir, write_dir, d, L):
+    """Turns two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, each with
+    --copy-calibration) into the counter summary: per-dispatch KiB of the limb GEMM and the
+    scale factors that make the 1 GiB calibration copy read and write exactly 1 GiB."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        rows = list(csv.DictReader(open(os.path.join(path, "p_counter_collection.csv"))))
+        gemm = [float(r["Counter_Value"]) for r in rows
+                if r["Counter_Name"] == counter and "gemm_i8_kernel" in r["Kernel_Name"]]
+        copy = [float(r["Counter_Value"]) for r in rows
+                if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]]
+        return statistics.mean(gemm), statistics.mean(copy)
+
+    fetch, fcopy = per_kernel(fetch_dir, "FETCH_SIZE")
+    write, wcopy = per_kernel(write_dir, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    out = {"kernel_source_sha256": kernel_source_hash(), "d": d, "primes": L,
+           "fetch_kib": fetch, "write_kib": write,
+           "fetch_scale": gib_kib / fcopy, "write_scale": gib_kib / wcopy,
+           "copy_calibration_kib": {"fetch": fcopy, "write": wcopy, "bytes_copied": 1 << 30}}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    return out
 
 
 def _time_steps(fn, steps, warmup):
@@ -133,6 +191,9 @@ def run_batch(args):
 
 def main():
     args = _parse()
+    if args.summarize_counters:
+        print(json.dumps(summarize_counters(*args.summarize_counters, args.d, args.primes)))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the CP-MM path has no multi-GPU leg); "
               f"got --gpus {args.gpus}", file=sys.stderr)
@@ -201,7 +262,8 @@ def main():
                    "m": d, "k": d, "n": d, "primes": L, "prime_bits": args.bits, "form": "int8",
                    "digits": [plan["p_limbs"], plan["x_limbs"]]},
         "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": INT8_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tops / INT8_PEAK_TOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved_tops / INT8_PEAK_TOPS,
+                     "traffic": measured_traffic(d, L),
                      "kernel": "gemm_i8_kernel", "avg_launch_ms": gemm_ms, "launches": n_gemm,
                      "ops_per_launch": ops, "op": "int8 MAC x 2"},
         "kernels_ms": {"gemm_i8": gemm_ms, "split_p": ms_sp / max(n_sp, 1),

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -34,8 +35,11 @@ struct BatchLayout {
     std::vector<BatchProb> probs;
     std::vector<BatchSeg> segs;
     int64_t total_items = 0;
+    int n_chunks = 1;
+    int64_t chunk_begin[kMaxChunks + 1] = {0};
     // workspace offsets (bytes) relative to the workspace base
     size_t off_pjobs = 0, off_xjobs = 0, off_probs = 0, off_segs = 0, off_counter = 0, off_digits = 0;
+    size_t off_pmap = 0, off_xmap = 0;  // workgroup -> job maps of the two split launches
     size_t bytes = 0;
 };
 
@@ -137,6 +141,28 @@ hlb_status build_layout(const hlb_cpmm_problem *probs, int count, const uint64_t
         lay.probs.push_back(bp);
     }
     if (lay.total_items > INT32_MAX || lay.p_wgs > INT32_MAX || lay.x_wgs > INT32_MAX) return HLB_EINVAL;
+    // cut the work list into n_chunks contiguous chunks of about equal cost (a tile costs
+    // its K blocks plus about two blocks of prologue and epilogue)
+    int n_xcd = 8;
+    (void)device_ready(&n_xcd);
+    lay.n_chunks = std::max(1, std::min(n_xcd, kMaxChunks));
+    double total_cost = 0.0;
+    for (const BatchProb &bp : lay.probs) total_cost += (double)bp.tiles_m * bp.tiles_n * (bp.kblocks + 2);
+    int c = 1;
+    double acc = 0.0;  // cost of all items before the current problem
+    for (const BatchProb &bp : lay.probs) {
+        const double per = bp.kblocks + 2.0;
+        const int64_t items = (int64_t)bp.tiles_m * bp.tiles_n;
+        // every cut whose target cost falls inside this problem
+        while (c < lay.n_chunks && acc + items * per >= total_cost * c / lay.n_chunks) {
+            const double need = total_cost * c / lay.n_chunks - acc;
+            const int64_t i = std::min<int64_t>(items, std::max<int64_t>(0, (int64_t)std::ceil(need / per)));
+            lay.chunk_begin[c++] = bp.item_start + i;
+        }
+        acc += items * per;
+    }
+    for (; c <= lay.n_chunks; ++c) lay.chunk_begin[c] = lay.total_items;
+    lay.chunk_begin[lay.n_chunks] = lay.total_items;
     size_t off = 0;
     lay.off_pjobs = off;
     off = align_up(off + lay.pjobs.size() * sizeof(SplitJob), 256);
@@ -148,6 +174,10 @@ hlb_status build_layout(const hlb_cpmm_problem *probs, int count, const uint64_t
     off = align_up(off + lay.segs.size() * sizeof(BatchSeg), 256);
     lay.off_counter = off;
     off = align_up(off + 256, 256);
+    lay.off_pmap = off;
+    off = align_up(off + (size_t)lay.p_wgs * sizeof(int32_t), 256);
+    lay.off_xmap = off;
+    off = align_up(off + (size_t)lay.x_wgs * sizeof(int32_t), 256);
     lay.off_digits = off;
     lay.bytes = off + digit_off;
     return HLB_OK;
@@ -171,6 +201,16 @@ std::vector<char> descriptor_image(const BatchLayout &lay) {
     std::memcpy(img.data() + lay.off_xjobs, lay.xjobs.data(), lay.xjobs.size() * sizeof(SplitJob));
     std::memcpy(img.data() + lay.off_probs, lay.probs.data(), lay.probs.size() * sizeof(BatchProb));
     std::memcpy(img.data() + lay.off_segs, lay.segs.data(), lay.segs.size() * sizeof(BatchSeg));
+    // job j owns workgroups [wg_start_j, wg_start_{j+1}), the last job up to `total`
+    auto fill_map = [&](const std::vector<SplitJob> &jobs, size_t off, int64_t total) {
+        int32_t *map = (int32_t *)(img.data() + off);
+        for (size_t j = 0; j < jobs.size(); ++j) {
+            const int64_t stop = j + 1 < jobs.size() ? jobs[j + 1].wg_start : total;
+            for (int64_t w = jobs[j].wg_start; w < stop; ++w) map[w] = (int32_t)j;
+        }
+    };
+    fill_map(lay.pjobs, lay.off_pmap, lay.p_wgs);
+    fill_map(lay.xjobs, lay.off_xmap, lay.x_wgs);
     return img;
 }
 
@@ -180,24 +220,26 @@ hlb_status enqueue(const BatchLayout &lay, char *base, int grid, hipStream_t s) 
     std::memset(&a, 0, sizeof(a));
     a.probs = (const BatchProb *)(base + lay.off_probs);
     a.segs = (const BatchSeg *)(base + lay.off_segs);
-    a.counter = (unsigned int *)(base + lay.off_counter);
+    a.counters = (unsigned int *)(base + lay.off_counter);
     a.total_items = lay.total_items;
+    a.n_chunks = lay.n_chunks;
+    for (int i = 0; i <= lay.n_chunks; ++i) a.chunk_begin[i] = lay.chunk_begin[i];
     a.nprob = (int32_t)lay.probs.size();
     a.kfold = lay.fold ? lay.kfold : INT32_MAX;
     a.group_m = 4;
     {
         ProfScope ps("split_p", s);
-        if (launch_split_batch_i8(lay.dp, (const SplitJob *)(base + lay.off_pjobs), (int)lay.pjobs.size(), lay.p_wgs,
-                                  s) != hipSuccess)
+        if (launch_split_batch_i8(lay.dp, (const SplitJob *)(base + lay.off_pjobs),
+                                  (const int32_t *)(base + lay.off_pmap), lay.p_wgs, s) != hipSuccess)
             return HLB_EDEVICE;
     }
     {
         ProfScope ps("split_x", s);
-        if (launch_split_batch_i8(lay.dx, (const SplitJob *)(base + lay.off_xjobs), (int)lay.xjobs.size(), lay.x_wgs,
-                                  s) != hipSuccess)
+        if (launch_split_batch_i8(lay.dx, (const SplitJob *)(base + lay.off_xjobs),
+                                  (const int32_t *)(base + lay.off_xmap), lay.x_wgs, s) != hipSuccess)
             return HLB_EDEVICE;
     }
-    if (launch_reset_counter(a.counter, s) != hipSuccess) return HLB_EDEVICE;
+    if (launch_reset_counter(a.counters, s) != hipSuccess) return HLB_EDEVICE;
     ProfScope ps("batch_i8", s);
     if (launch_gemm_i8_batch(lay.dp, lay.dx, lay.fold, a, grid, s) != hipSuccess) return HLB_EDEVICE;
     return HLB_OK;
@@ -231,6 +273,7 @@ std::vector<uint64_t> signature(const hlb_cpmm_problem *probs, int count, const 
     sig.push_back((uint64_t)lay.dp);
     sig.push_back((uint64_t)lay.dx);
     sig.push_back((uint64_t)(lay.fold ? lay.kfold : 0));
+    sig.push_back((uint64_t)lay.n_chunks);
     for (const BatchProb &p : lay.probs) sig.push_back((uint64_t)p.cls);
     sig.push_back((uint64_t)L);
     for (int l = 0; l < L; ++l) sig.push_back(primes[l]);

@@ -151,12 +151,16 @@ struct BatchSeg {
     int32_t tile_begin, pad;
 };
 
+// The work list is cut into n_chunks contiguous chunks of about equal cost, one per XCD;
+// chunk x is [chunk_begin[x], chunk_begin[x+1]) and counters[x] hands out its items.
+constexpr int kMaxChunks = 16;
 struct BatchArgs {
     const BatchProb *probs;
     const BatchSeg *segs;
-    unsigned int *counter;  // next work item; zeroed by a reset kernel before each launch
+    unsigned int *counters;  // kMaxChunks counters, zeroed by a reset kernel before each launch
     int64_t total_items;
-    int32_t nprob, kfold, group_m, pad;
+    int64_t chunk_begin[kMaxChunks + 1];
+    int32_t nprob, kfold, group_m, n_chunks;
 };
 
 // Maps a workgroup id to (row tile, column tile).  Workgroups are dealt to the XCDs

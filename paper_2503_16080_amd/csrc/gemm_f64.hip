@@ -72,15 +72,30 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f64_kernel(const GemmArgs ar
     int64_t rp[4];
     uint64_t rx[4];
     auto gload = [&](int kb) {
+        // loads from clamped in-bounds addresses, then selects
         const int64_t k0 = (int64_t)kb * T::BK;
         const int64_t row = m0 + pr;
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            rp[e] = (row < args.m && k0 + pk + e < K) ? args.P[row * args.ldp + k0 + pk + e] : 0;
+        const int64_t rowc = row < args.m ? row : args.m - 1;
         const int64_t kr = k0 + xk;
+        const int64_t krc = kr < K ? kr : K - 1;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            rx[e] = (kr < K && n0 + xn + e < sg.n) ? sg.X[kr * sg.ldx + n0 + xn + e] : 0;
+        for (int e = 0; e < 4; ++e) {
+            rp[e] = args.P[rowc * args.ldp + (k0 + pk + e < K ? k0 + pk + e : K - 1)];
+            const int64_t col = n0 + xn + e;
+            rx[e] = sg.X[krc * sg.ldx + (col < sg.n ? col : sg.n - 1)];
+        }
+        // the empty asm consumes every loaded value unconditionally, so the masks below
+        // stay selects instead of becoming conditional loads (a branch and a wait each)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            asm volatile("" : "+v"(rp[e]));
+            asm volatile("" : "+v"(rx[e]));
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            rp[e] = (row < args.m && k0 + pk + e < K) ? rp[e] : 0;
+            rx[e] = (kr < K && n0 + xn + e < sg.n) ? rx[e] : 0;
+        }
     };
     auto lstore = [&](int buf) {
         double *lp = lds + buf * T::STAGE;

@@ -32,6 +32,15 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kSplitRowPad = 68;  // LDS row stride in bytes: 64 + 4 keeps dword writes conflict-free
 constexpr int kSplitLds = 7 * 128 * kSplitRowPad;
 
+// Keeps the compiler from turning a load whose value a later select may discard back into
+// a conditional load (a branch per element, each waiting for its load): the empty asm
+// consumes every loaded value unconditionally, after all the loads have been issued.
+template <int N>
+__device__ __forceinline__ void pin_loaded(uint64_t (&v)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(v[i]));
+}
+
 template <int D>
 __device__ __forceinline__ void digits4(const uint64_t (&x)[4], uint32_t (&out)[D]) {
     constexpr uint64_t bias = digit_bias(D);
@@ -69,21 +78,35 @@ __device__ __forceinline__ void split_stage2(const uint8_t *lds, int8_t *tile_ou
 }
 
 // One (row tile rb, k block kb) of the plaintext side: rows of P (signed int64 or residues).
+// Every thread first issues all its loads (4 consecutive K elements of R/16 rows), from
+// clamped in-bounds addresses, and only then masks and splits them: a conditional load
+// would become a branch that waits for each load before issuing the next.
 template <int D, int R>
 __device__ __forceinline__ void split_rows_tile(const int64_t *__restrict__ P, int64_t ldp, int64_t m,
                                                 int64_t k, int kblocks, int rb, int kb, int8_t *out,
                                                 uint8_t *lds) {
+    constexpr int IT = R / (kThreads / 16);
     const int t = threadIdx.x;
     const int quad = t & 15;  // 4 consecutive K elements
-#pragma unroll 1
-    for (int r = t >> 4; r < R; r += kThreads / 16) {
-        const int64_t row = (int64_t)rb * R + r;
-        const int64_t k0 = (int64_t)kb * kBK8 + quad * 4;
-        uint64_t x[4];
+    const int64_t k0 = (int64_t)kb * kBK8 + quad * 4;
+    uint64_t x[IT][4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) x[e] = (row < m && k0 + e < k) ? (uint64_t)P[row * ldp + k0 + e] : 0;
+    for (int it = 0; it < IT; ++it) {
+        const int64_t row = (int64_t)rb * R + (t >> 4) + it * (kThreads / 16);
+        const int64_t rc = row < m ? row : m - 1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[it][e] = (uint64_t)P[rc * ldp + (k0 + e < k ? k0 + e : k - 1)];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) pin_loaded(x[it]);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int r = (t >> 4) + it * (kThreads / 16);
+        const int64_t row = (int64_t)rb * R + r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[it][e] = (row < m && k0 + e < k) ? x[it][e] : 0;
         uint32_t d[D];
-        digits4<D>(x, d);
+        digits4<D>(x[it], d);
 #pragma unroll
         for (int j = 0; j < D; ++j) *(uint32_t *)(lds + (j * R + r) * kSplitRowPad + quad * 4) = d[j];
     }
@@ -91,23 +114,36 @@ __device__ __forceinline__ void split_rows_tile(const int64_t *__restrict__ P, i
     split_stage2<D, R>(lds, out + ((int64_t)rb * kblocks + kb) * (D * R * kBK8));
 }
 
-// One (column tile cb, k block kb) of the ciphertext side: columns of X (transposed).
+// One (column tile cb, k block kb) of the ciphertext side: columns of X (transposed).  Each
+// lane owns one column and loads 4 consecutive rows at a time, so lanes with consecutive
+// columns read consecutive addresses; loads are issued first as above.
 template <int D, int R>
 __device__ __forceinline__ void split_cols_tile(const uint64_t *__restrict__ X, int64_t ldx, int64_t k,
                                                 int64_t n, int kblocks, int cb, int kb, int8_t *out,
                                                 uint8_t *lds) {
+    constexpr int quads_in_flight = kThreads / R;  // K quads handled per pass
+    constexpr int IT = 16 / quads_in_flight;
     const int t = threadIdx.x;
-    constexpr int quads_in_flight = kThreads / R;  // K quads handled per pass, one column per lane
-#pragma unroll 1
-    for (int qd = t / R; qd < 16; qd += quads_in_flight) {
-        const int c = t % R;
-        const int64_t col = (int64_t)cb * R + c;
-        const int64_t k0 = (int64_t)kb * kBK8 + qd * 4;
-        uint64_t x[4];
+    const int c = t % R;
+    const int64_t col = (int64_t)cb * R + c;
+    const int64_t cc = col < n ? col : n - 1;
+    uint64_t x[IT][4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) x[e] = (col < n && k0 + e < k) ? X[(k0 + e) * ldx + col] : 0;
+    for (int it = 0; it < IT; ++it) {
+        const int64_t k0 = (int64_t)kb * kBK8 + (t / R + it * quads_in_flight) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[it][e] = X[(k0 + e < k ? k0 + e : k - 1) * ldx + cc];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) pin_loaded(x[it]);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int qd = t / R + it * quads_in_flight;
+        const int64_t k0 = (int64_t)kb * kBK8 + qd * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[it][e] = (col < n && k0 + e < k) ? x[it][e] : 0;
         uint32_t d[D];
-        digits4<D>(x, d);
+        digits4<D>(x[it], d);
 #pragma unroll
         for (int j = 0; j < D; ++j) *(uint32_t *)(lds + (j * R + c) * kSplitRowPad + qd * 4) = d[j];
     }
@@ -131,19 +167,14 @@ __global__ __launch_bounds__(kThreads) void split_cols_i8(const uint64_t *__rest
     split_cols_tile<D, R>(X, ldx, k, n, kblocks, blockIdx.x / kblocks, blockIdx.x % kblocks, out, lds);
 }
 
-// Batched splits: one launch covers every job of a batch; workgroup w finds its job by
-// binary search over the jobs' first workgroup indices.
+// Batched splits: one launch covers every job of a batch; workgroup w finds its job in a
+// host-built workgroup -> job map.
 template <int D>
-__global__ __launch_bounds__(kThreads) void split_batch_i8(const SplitJob *__restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(kThreads) void split_batch_i8(const SplitJob *__restrict__ jobs,
+                                                           const int32_t *__restrict__ wg_job) {
     __shared__ uint8_t lds[kSplitLds];
     const int64_t w = blockIdx.x;
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].wg_start <= w) lo = mid;
-        else hi = mid - 1;
-    }
-    const int ji = lo;
+    const int ji = wg_job[w];  // one load instead of a search over the jobs
     const SplitJob &j = jobs[ji];
     const int64_t local = w - j.wg_start;
     const int tile = (int)(local / j.kblocks), kb = (int)(local % j.kblocks);
@@ -417,23 +448,36 @@ __global__ __launch_bounds__(T::THREADS, 1) void gemm_i8_kernel(const GemmArgs a
 }
 
 // ---------------------------------------------------------------------------------------
-// Persistent batch kernel: a fixed grid of workgroups pulls output tiles from one atomic
-// counter.  Work items are ordered by the host (largest K first); each item maps to a
-// problem by binary search over the problems' first work-item indices, then to a tile of
-// that problem in its own tile class.  Every workgroup exits when the counter passes the
-// end of the list.
+// Persistent batch kernel: a fixed grid of workgroups (one per CU) pulls output tiles from
+// a work list ordered by the host (largest K first).  The list is cut into one contiguous
+// chunk of about equal cost per XCD; workgroups are dealt to XCDs round-robin, so workgroup
+// w serves chunk w % n_chunks first, and neighbouring tiles (which share plaintext and
+// ciphertext panels) stay in one XCD's L2.  A workgroup whose chunk is exhausted moves on
+// to the next chunk (work stealing) and exits after finding all n_chunks exhausted.  Each
+// item maps to a problem by binary search over the problems' first work-item indices, then
+// to a tile of that problem in its own tile class.
 // ---------------------------------------------------------------------------------------
 template <int DP, int DX, bool FOLD>
 __global__ __launch_bounds__(256 * 2, 1) void gemm_i8_batch_kernel(const BatchArgs args) {
     constexpr int L0 = Class0<DP, DX>::LDS, L1 = Class1<DP, DX>::LDS;
     __shared__ __attribute__((aligned(16))) int8_t lds[L0 > L1 ? L0 : L1];
     __shared__ int64_t item;
-    for (;;) {
-        if (threadIdx.x == 0) item = (int64_t)atomicAdd(args.counter, 1u);
+    int chunk = blockIdx.x % args.n_chunks;
+    int exhausted = 0;
+    while (exhausted < args.n_chunks) {
+        if (threadIdx.x == 0) {
+            const int64_t t = args.chunk_begin[chunk] + (int64_t)atomicAdd(&args.counters[chunk], 1u);
+            item = t < args.chunk_begin[chunk + 1] ? t : -1;
+        }
         __syncthreads();
         const int64_t t = item;
         __syncthreads();  // everyone has read `item` before thread 0 overwrites it
-        if (t >= args.total_items) return;
+        if (t < 0) {
+            chunk = chunk + 1 == args.n_chunks ? 0 : chunk + 1;
+            ++exhausted;
+            continue;
+        }
+        exhausted = 0;
         int lo = 0, hi = args.nprob - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -479,8 +523,8 @@ __global__ __launch_bounds__(256 * 2, 1) void gemm_i8_batch_kernel(const BatchAr
     }
 }
 
-__global__ void reset_counter_kernel(unsigned int *counter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+__global__ void reset_counter_kernel(unsigned int *counters) {
+    if (threadIdx.x < kMaxChunks && blockIdx.x == 0) counters[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -521,12 +565,13 @@ hipError_t launch_split_cols_i8(int D, int R, const uint64_t *X, int64_t ldx, in
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_split_batch_i8(int D, const SplitJob *jobs, int njobs, int64_t total_wgs, hipStream_t s) {
-    if (njobs <= 0 || total_wgs <= 0) return hipSuccess;
+hipError_t launch_split_batch_i8(int D, const SplitJob *jobs, const int32_t *wg_job, int64_t total_wgs,
+                                 hipStream_t s) {
+    if (total_wgs <= 0) return hipSuccess;
     if (total_wgs > INT32_MAX) return hipErrorInvalidValue;
-    if (D == 3) hipLaunchKernelGGL(split_batch_i8<3>, dim3((unsigned)total_wgs), dim3(kThreads), 0, s, jobs, njobs);
-    else if (D == 6) hipLaunchKernelGGL(split_batch_i8<6>, dim3((unsigned)total_wgs), dim3(kThreads), 0, s, jobs, njobs);
-    else if (D == 7) hipLaunchKernelGGL(split_batch_i8<7>, dim3((unsigned)total_wgs), dim3(kThreads), 0, s, jobs, njobs);
+    if (D == 3) hipLaunchKernelGGL(split_batch_i8<3>, dim3((unsigned)total_wgs), dim3(kThreads), 0, s, jobs, wg_job);
+    else if (D == 6) hipLaunchKernelGGL(split_batch_i8<6>, dim3((unsigned)total_wgs), dim3(kThreads), 0, s, jobs, wg_job);
+    else if (D == 7) hipLaunchKernelGGL(split_batch_i8<7>, dim3((unsigned)total_wgs), dim3(kThreads), 0, s, jobs, wg_job);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

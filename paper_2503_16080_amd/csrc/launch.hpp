@@ -25,7 +25,8 @@ hipError_t launch_split_cols_i8(int D, int R, const uint64_t *X, int64_t ldx, in
 hipError_t launch_gemm_i8(int dp, int dx, int cls, const GemmArgs &a, hipStream_t s);
 // Batch path: all splits of a batch in one launch, the work counter reset, and the
 // persistent GEMM over every tile of every problem.
-hipError_t launch_split_batch_i8(int D, const SplitJob *jobs, int njobs, int64_t total_wgs, hipStream_t s);
+hipError_t launch_split_batch_i8(int D, const SplitJob *jobs, const int32_t *wg_job, int64_t total_wgs,
+                                 hipStream_t s);
 hipError_t launch_reset_counter(unsigned int *counter, hipStream_t s);
 hipError_t launch_gemm_i8_batch(int dp, int dx, bool fold, const BatchArgs &a, int grid, hipStream_t s);
 
