@@ -89,6 +89,35 @@ hlb_status hlb_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB,
                      const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L,
                      uint64_t *PA, uint64_t *PB, int form, void *stream);
 
+/*
+ * The plaintext-product core of the ciphertext-ciphertext product (Algorithm alg:ccmm, step
+ * 2): for every prime l < L, the four Mod-PP-MMs
+ *     C00[l] = A[l] At[l],  C01[l] = A[l] Bt[l],  C10[l] = B[l] At[l],  C11[l] = B[l] Bt[l]
+ * (mod primes[l]), i.e. [A; B] * [At Bt], with both operands full residues.  Each operand is
+ * split into digits once and shared by the two products it enters.
+ *   A, B:   [L][m][k] residues, dense;  At, Bt: [L][k][n] residues, dense;
+ *   C00, C01, C10, C11: [L][m][n] outputs, dense.
+ * The transposes, relinearisation and rescaling around this step are not part of the call.
+ */
+hlb_status hlb_ccmm_pp_core(int64_t m, int64_t k, int64_t n, const uint64_t *A, const uint64_t *B,
+                            const uint64_t *At, const uint64_t *Bt, const uint64_t *primes, int L,
+                            uint64_t *C00, uint64_t *C01, uint64_t *C10, uint64_t *C11, int form,
+                            void *stream);
+
+/*
+ * Rescale by the last RNS prime (the Rescale step of Algorithm alg:pcmm, with the scaling
+ * factor equal to the dropped prime, which then divides the modulus as Section 5 assumes):
+ * for an integer x given by its residues X[l] = x mod primes[l], l < L, returns the residues
+ * of floor(x / q + 1/2), q = primes[L-1], modulo each of the first L-1 primes:
+ *     Y[l] = (x - c) * q^{-1} mod primes[l],   c = the representative of x mod q in
+ *     (-q/2, q/2] (ties at q/2 taken upward),
+ * which is exact and independent of the representative of x modulo the product of primes.
+ *   X: [L][count] residues (count = rows * cols of each matrix, dense), Y: [L-1][count].
+ * Requires L >= 2 and primes[L-1] invertible modulo every other prime (HLB_EINVAL if not).
+ */
+hlb_status hlb_rescale(int64_t count, const uint64_t *X, const uint64_t *primes, int L, uint64_t *Y,
+                       void *stream);
+
 /* One CP-MM of a batch: the fields mean what the hlb_cp_mm arguments of the same names
  * mean (dense layouts [L][k][nA], [L][k][nB], [L][m][nA], [L][m][nB]; P row stride ldp). */
 typedef struct {

@@ -239,3 +239,30 @@ def precision_bits(M, Mt) -> float:
     if err == 0.0:
         return float("inf")
     return float(np.log2(top) - np.log2(err))
+
+
+def rescale(X, primes):
+    """Rescale by the last prime, by definition: for the integer x with residues X[l] (any
+    representative modulo the product of the primes), the residues of floor(x / q + 1/2)
+    modulo the first L-1 primes, q = primes[L-1] (Section 2.2 Rescale, with the scaling
+    factor equal to the dropped prime as Section 5 assumes).  Exact big-integer arithmetic:
+    floor(x / q + 1/2) = floor((2x + q) / (2q)).
+    """
+    primes = [int(p) for p in primes]
+    q = primes[-1]
+    x = crt_lift_centered(X, primes)          # object array of Python ints
+    y = (2 * x + q) // (2 * q)                 # Python floor division of exact integers
+    return np.stack([(y % ql).astype(np.uint64) for ql in primes[:-1]])
+
+
+def ccmm_pp_core(A, B, At, Bt, primes):
+    """The four Mod-PP-MMs of the ciphertext-ciphertext product's plaintext core (Algorithm
+    alg:ccmm step 2): [A; B] * [At Bt] modulo each prime, returned as (C00, C01, C10, C11)."""
+    out = [[], [], [], []]
+    for l, q in enumerate(primes):
+        q = int(q)
+        out[0].append(mod_pp_mm(q, A[l], At[l]))
+        out[1].append(mod_pp_mm(q, A[l], Bt[l]))
+        out[2].append(mod_pp_mm(q, B[l], At[l]))
+        out[3].append(mod_pp_mm(q, B[l], Bt[l]))
+    return tuple(np.stack(o) for o in out)

@@ -24,6 +24,7 @@ __all__ = [
     "hlb_plaintext_absmax", "hlb_plan", "hlb_set_option", "hlb_profile_read",
     "hlb_profile_reset", "hlb_release", "hlb_status_str", "hlb_test_encode",
     "hlb_test_encrypt", "hlb_test_decrypt", "hlb_tune_set", "hlb_tune_load", "hlb_tune_class",
+    "hlb_ccmm_pp_core", "hlb_rescale", "ccmm_pp_core", "rescale",
     "mod_pp_mm", "cp_mm", "cp_mm_batch", "validate_residues", "plaintext_absmax", "plan",
     "set_option", "profile_read", "profile_reset", "release",
 ]
@@ -91,6 +92,8 @@ def load():
             "hlb_test_encode": (ci, [vp, i64, ctypes.c_double, vp, vp]),
             "hlb_test_encrypt": (ci, [i64, i64, vp, vp, vp, vp, ci, vp, vp]),
             "hlb_test_decrypt": (ci, [i64, i64, vp, vp, vp, vp, ci, vp, vp]),
+            "hlb_ccmm_pp_core": (ci, [i64, i64, i64, vp, vp, vp, vp, vp, ci, vp, vp, vp, vp, ci, vp]),
+            "hlb_rescale": (ci, [i64, vp, vp, ci, vp, vp]),
             "hlb_tune_set": (ci, [ci, ci, ci, ci, ci]),
             "hlb_tune_load": (ci, [ctypes.c_char_p]),
             "hlb_tune_class": (ci, [ci, i64, i64, i64]),
@@ -223,6 +226,39 @@ def hlb_cp_mm_batch(problems, primes: Sequence[int], form="int8", stream=None):
     return outs
 
 
+def hlb_ccmm_pp_core(A, B, At, Bt, primes: Sequence[int], form="auto", stream=None):
+    """[A; B] * [At Bt] modulo each prime (CC-MM plaintext core): returns (C00, C01, C10, C11),
+    each [L, m, n].  A, B: [L, m, k]; At, Bt: [L, k, n]; all contiguous residue tensors."""
+    for t, nm in ((A, "A"), (B, "B"), (At, "At"), (Bt, "Bt")):
+        _dev64(t, nm)
+        if t.dim() != 3 or not t.is_contiguous():
+            raise ValueError(f"{nm} must be a contiguous [L, rows, cols] tensor")
+    L = len(primes)
+    _, m, k = A.shape
+    n = At.shape[2]
+    if B.shape != A.shape or Bt.shape != At.shape or At.shape[1] != k or A.shape[0] != L or At.shape[0] != L:
+        raise ValueError("shapes must be A, B: [L, m, k] and At, Bt: [L, k, n]")
+    outs = [torch.empty((L, m, n), dtype=torch.int64, device=A.device) for _ in range(4)]
+    qs = (ctypes.c_uint64 * max(L, 1))(*[int(q) for q in primes])
+    _check(load().hlb_ccmm_pp_core(m, k, n, A.data_ptr(), B.data_ptr(), At.data_ptr(), Bt.data_ptr(), qs, L,
+                                   *[o.data_ptr() for o in outs], _form(form), _stream(stream)), "ccmm_pp_core")
+    return tuple(outs)
+
+
+def hlb_rescale(X, primes: Sequence[int], stream=None):
+    """Rescale by the last prime: X is [L, ...] residues of integers x; returns [L-1, ...]
+    residues of floor(x / q_{L-1} + 1/2)."""
+    _dev64(X, "X")
+    if not X.is_contiguous() or X.shape[0] != len(primes):
+        raise ValueError("X must be contiguous with leading dimension L = len(primes)")
+    L = len(primes)
+    count = X[0].numel() if L else 0
+    Y = torch.empty((max(L - 1, 0),) + tuple(X.shape[1:]), dtype=torch.int64, device=X.device)
+    qs = (ctypes.c_uint64 * max(L, 1))(*[int(q) for q in primes])
+    _check(load().hlb_rescale(count, X.data_ptr(), qs, L, Y.data_ptr(), _stream(stream)), "rescale")
+    return Y
+
+
 def hlb_validate_residues(X: torch.Tensor, q: int, stream=None) -> int:
     """Synchronous: returns -1 when every entry is < q, else the first offending index."""
     _dev64(X, "X")
@@ -317,6 +353,8 @@ def hlb_test_decrypt(A: torch.Tensor, B: torch.Tensor, S: torch.Tensor, primes, 
 
 
 # short aliases
+ccmm_pp_core = hlb_ccmm_pp_core
+rescale = hlb_rescale
 mod_pp_mm = hlb_mod_pp_mm
 cp_mm = hlb_cp_mm
 cp_mm_batch = hlb_cp_mm_batch

@@ -299,119 +299,125 @@ void ws_free(void *p, hipStream_t s) {
 // ---------------------------------------------------------------------------------------
 // One GEMM launch over up to kMaxSegs output segments sharing the left operand.
 // ---------------------------------------------------------------------------------------
-struct OutSpec {
-    uint64_t *C;
-    const uint64_t *X;  // right operand (k x n, row stride ldx)
-    int64_t ldc, ldx, n;
-    uint64_t q;
-};
-
-// Runs C_s = P * X_s mod q_s for every segment s (left operand shared): the plaintext split
-// once, the right operands split per segment, then GEMM launches of <= kMaxSegs segments.
-hlb_status run_products(const Plan &pl, const int64_t *P, int64_t ldp, int64_t m, int64_t k,
-                        const std::vector<OutSpec> &outs, int n_xcd, hipStream_t s) {
-    if (m == 0 || outs.empty()) return HLB_OK;
+// Runs C[l][r] = L_l * X_r mod q_r for every left operand L_l and right operand X_r.  Each
+// right operand is split once and shared by all left operands; each left operand is split
+// once and shared by all right operands; then one GEMM launch per left operand covers up to
+// kMaxSegs right operands (more are chunked).
+hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, const std::vector<RightSpec> &rights,
+                        int64_t k, int n_xcd, hipStream_t s) {
+    if (lefts.empty() || rights.empty()) return HLB_OK;
+    int64_t mmax = 0;
+    for (const LeftSpec &L : lefts) mmax = std::max(mmax, L.m);
+    if (mmax == 0) return HLB_OK;
     if (k == 0) {
-        for (const OutSpec &o : outs)
-            if (o.n > 0 && hipMemset2DAsync(o.C, o.ldc * 8, 0, o.n * 8, m, s) != hipSuccess) return HLB_EDEVICE;
+        for (const LeftSpec &L : lefts)
+            for (size_t r = 0; r < rights.size(); ++r)
+                if (L.m > 0 && rights[r].n > 0 &&
+                    hipMemset2DAsync(L.C[r], L.ldc[r] * 8, 0, rights[r].n * 8, L.m, s) != hipSuccess)
+                    return HLB_EDEVICE;
         return HLB_OK;
     }
-    const int64_t tiles_m = (m + pl.bm - 1) / pl.bm;
+    const int64_t tiles_mmax = (mmax + pl.bm - 1) / pl.bm;
     const int64_t kblocks = (k + pl.bk - 1) / pl.bk;
     const int64_t kfold = std::max<int64_t>(1, pl.kchunk / pl.bk);
-    std::vector<int64_t> seg_tiles(outs.size());
+    std::vector<int64_t> seg_tiles(rights.size());
     int64_t tiles_total = 0;
-    for (size_t i = 0; i < outs.size(); ++i) {
-        seg_tiles[i] = (outs[i].n + pl.bn - 1) / pl.bn;
+    for (size_t i = 0; i < rights.size(); ++i) {
+        seg_tiles[i] = (rights[i].n + pl.bn - 1) / pl.bn;
         tiles_total += seg_tiles[i];
     }
     // grid sizes and in-kernel tile indices are 32-bit
-    if (kblocks > INT32_MAX / 2 || tiles_total > INT32_MAX / 2 || tiles_m * tiles_total > INT32_MAX / 2)
+    if (kblocks > INT32_MAX / 2 || tiles_total > INT32_MAX / 2 || tiles_mmax * tiles_total > INT32_MAX / 2)
         return HLB_EINVAL;
 
     void *wsP = nullptr, *wsX = nullptr;
     const int64_t p_tile = (int64_t)pl.np * pl.bm * kBK8, x_tile = (int64_t)pl.nx * pl.bn * kBK8;
+    auto release = [&]() {
+        ws_free(wsP, s);
+        ws_free(wsX, s);
+    };
     if (pl.form == HLB_FORM_INT8) {
-        hlb_status st = ws_alloc(&wsP, (size_t)(tiles_m * kblocks * p_tile), s);
+        hlb_status st = ws_alloc(&wsP, (size_t)(tiles_mmax * kblocks * p_tile), s);
         if (st != HLB_OK) return st;
         st = ws_alloc(&wsX, (size_t)(tiles_total * kblocks * x_tile), s);
         if (st != HLB_OK) {
-            ws_free(wsP, s);
+            release();
             return st;
         }
-        {
-            ProfScope ps("split_p", s);
-            if (launch_split_rows_i8(pl.np, pl.bm, P, ldp, m, k, (int)tiles_m, (int)kblocks, (int8_t *)wsP, s) !=
-                hipSuccess) {
-                ws_free(wsP, s);
-                ws_free(wsX, s);
-                return HLB_EDEVICE;
-            }
-        }
         int64_t t0 = 0;
-        for (size_t i = 0; i < outs.size(); ++i) {
+        for (size_t i = 0; i < rights.size(); ++i) {
             ProfScope ps("split_x", s);
             int8_t *dst = (int8_t *)wsX + t0 * kblocks * x_tile;
-            if (launch_split_cols_i8(pl.nx, pl.bn, outs[i].X, outs[i].ldx, k, outs[i].n, (int)seg_tiles[i],
+            if (launch_split_cols_i8(pl.nx, pl.bn, rights[i].X, rights[i].ldx, k, rights[i].n, (int)seg_tiles[i],
                                      (int)kblocks, dst, s) != hipSuccess) {
-                ws_free(wsP, s);
-                ws_free(wsX, s);
+                release();
                 return HLB_EDEVICE;
             }
             t0 += seg_tiles[i];
         }
     }
 
-    hlb_status result = HLB_OK;
-    int64_t tile_base = 0;
-    for (size_t first = 0; first < outs.size(); first += kMaxSegs) {
-        const size_t last = std::min(outs.size(), first + kMaxSegs);
-        GemmArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.Pd = (const int8_t *)wsP;
-        a.Xd = wsX ? (const int8_t *)wsX + tile_base * kblocks * x_tile : nullptr;
-        a.P = P;
-        a.ldp = ldp;
-        a.m = m;
-        a.k = k;
-        a.kblocks = (int)kblocks;
-        a.kfold = kfold >= kblocks ? (int)kblocks + 1 : (int)kfold;  // >= kblocks: no fold
-        a.tiles_m = (int)tiles_m;
-        a.group_m = 4;
-        a.n_xcd = n_xcd;
-        a.limb_bits = pl.limb_bits;
-        int32_t tb = 0;
-        for (size_t i = first; i < last; ++i) {
-            Seg &sg = a.seg[a.nseg++];
-            sg.C = outs[i].C;
-            sg.X = outs[i].X;
-            sg.ldc = outs[i].ldc;
-            sg.ldx = outs[i].ldx;
-            sg.n = outs[i].n;
-            fill_seg(sg, outs[i].q, pl.limb_bits);
-            sg.tile_begin = tb;
-            sg.tiles = (int32_t)seg_tiles[i];
-            tb += sg.tiles;
-        }
-        a.tiles_n = tb;
-        tile_base += tb;
-        if (tb == 0) continue;
-        hipError_t e;
+    for (const LeftSpec &L : lefts) {
+        if (L.m == 0) continue;
+        const int64_t tiles_m = (L.m + pl.bm - 1) / pl.bm;
         if (pl.form == HLB_FORM_INT8) {
-            ProfScope ps("gemm_i8", s);
-            e = launch_gemm_i8(pl.np, pl.nx, pl.cls, a, s);
-        } else {
-            ProfScope ps("gemm_f64", s);
-            e = launch_gemm_f64(pl.np, pl.nx, a, s);
+            // stream order: this split runs after the previous left operand's GEMM has read wsP
+            ProfScope ps("split_p", s);
+            if (launch_split_rows_i8(pl.np, pl.bm, L.P, L.ldp, L.m, k, (int)tiles_m, (int)kblocks, (int8_t *)wsP,
+                                     s) != hipSuccess) {
+                release();
+                return HLB_EDEVICE;
+            }
         }
-        if (e != hipSuccess) {
-            result = HLB_EDEVICE;
-            break;
+        int64_t tile_base = 0;
+        for (size_t first = 0; first < rights.size(); first += kMaxSegs) {
+            const size_t last = std::min(rights.size(), first + kMaxSegs);
+            GemmArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.Pd = (const int8_t *)wsP;
+            a.Xd = wsX ? (const int8_t *)wsX + tile_base * kblocks * x_tile : nullptr;
+            a.P = L.P;
+            a.ldp = L.ldp;
+            a.m = L.m;
+            a.k = k;
+            a.kblocks = (int)kblocks;
+            a.kfold = kfold >= kblocks ? (int)kblocks + 1 : (int)kfold;  // >= kblocks: no fold
+            a.tiles_m = (int)tiles_m;
+            a.group_m = 4;
+            a.n_xcd = n_xcd;
+            a.limb_bits = pl.limb_bits;
+            int32_t tb = 0;
+            for (size_t i = first; i < last; ++i) {
+                Seg &sg = a.seg[a.nseg++];
+                sg.C = L.C[i];
+                sg.X = rights[i].X;
+                sg.ldc = L.ldc[i];
+                sg.ldx = rights[i].ldx;
+                sg.n = rights[i].n;
+                fill_seg(sg, rights[i].q, pl.limb_bits);
+                sg.tile_begin = tb;
+                sg.tiles = (int32_t)seg_tiles[i];
+                tb += sg.tiles;
+            }
+            a.tiles_n = tb;
+            tile_base += tb;
+            if (tb == 0) continue;
+            hipError_t e;
+            if (pl.form == HLB_FORM_INT8) {
+                ProfScope ps("gemm_i8", s);
+                e = launch_gemm_i8(pl.np, pl.nx, pl.cls, a, s);
+            } else {
+                ProfScope ps("gemm_f64", s);
+                e = launch_gemm_f64(pl.np, pl.nx, a, s);
+            }
+            if (e != hipSuccess) {
+                release();
+                return HLB_EDEVICE;
+            }
         }
     }
-    ws_free(wsP, s);
-    ws_free(wsX, s);
-    return result;
+    release();
+    return HLB_OK;
 }
 
 hlb_status measure_absmax(const int64_t *P, int64_t m, int64_t k, int64_t ld, int64_t *out, hipStream_t s) {
@@ -478,8 +484,9 @@ hlb_status hlb_mod_pp_mm(uint64_t q, int64_t m, int64_t k, int64_t n, const uint
     choose_class(&pl, m, n, k);
     int n_xcd = 8;
     if ((st = device_ready(&n_xcd)) != HLB_OK) return st;
-    std::vector<OutSpec> outs{{C, X, ldc, ldx, n, q}};
-    return run_products(pl, (const int64_t *)P, ldp, m, k, outs, n_xcd, (hipStream_t)stream);
+    std::vector<RightSpec> rights{{X, ldx, n, q}};
+    std::vector<LeftSpec> lefts{{(const int64_t *)P, ldp, m, {C}, {ldc}}};
+    return run_products(pl, lefts, rights, k, n_xcd, (hipStream_t)stream);
 }
 
 hlb_status hlb_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp,
@@ -508,12 +515,85 @@ hlb_status hlb_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t
     Plan pl;
     if ((st = plan(1, k, qmax, std::max<int64_t>(p_absmax, 1), form, &pl)) != HLB_OK) return st;
     choose_class(&pl, m, std::max(nA, nB), k);
-    std::vector<OutSpec> outs;
+    std::vector<RightSpec> rights;
+    LeftSpec left{P, ldp, m, {}, {}};
     for (int l = 0; l < L; ++l) {
-        if (nA > 0) outs.push_back({PA + (int64_t)l * m * nA, A + (int64_t)l * k * nA, nA, nA, nA, primes[l]});
-        if (nB > 0) outs.push_back({PB + (int64_t)l * m * nB, B + (int64_t)l * k * nB, nB, nB, nB, primes[l]});
+        if (nA > 0) {
+            rights.push_back({A + (int64_t)l * k * nA, nA, nA, primes[l]});
+            left.C.push_back(PA + (int64_t)l * m * nA);
+            left.ldc.push_back(nA);
+        }
+        if (nB > 0) {
+            rights.push_back({B + (int64_t)l * k * nB, nB, nB, primes[l]});
+            left.C.push_back(PB + (int64_t)l * m * nB);
+            left.ldc.push_back(nB);
+        }
     }
-    return run_products(pl, P, ldp, m, k, outs, n_xcd, s);
+    return run_products(pl, {left}, rights, k, n_xcd, s);
+}
+
+hlb_status hlb_ccmm_pp_core(int64_t m, int64_t k, int64_t n, const uint64_t *A, const uint64_t *B,
+                            const uint64_t *At, const uint64_t *Bt, const uint64_t *primes, int L,
+                            uint64_t *C00, uint64_t *C01, uint64_t *C10, uint64_t *C11, int form, void *stream) {
+    if (m < 0 || k < 0 || n < 0 || L < 0 || L > 1024) return HLB_EINVAL;
+    if (L == 0 || m == 0 || n == 0) return HLB_OK;
+    if (!primes || !C00 || !C01 || !C10 || !C11) return HLB_EINVAL;
+    if (k > 0 && (!A || !B || !At || !Bt)) return HLB_EINVAL;
+    uint64_t qmax = 0;
+    for (int l = 0; l < L; ++l) {
+        if (check_modulus(primes[l]) != HLB_OK) return HLB_EINVAL;
+        qmax = std::max(qmax, primes[l]);
+    }
+    Plan pl;
+    hlb_status st = plan(0, k, qmax, 0, form, &pl);
+    if (st != HLB_OK) return st;
+    choose_class(&pl, m, n, k);
+    int n_xcd = 8;
+    if ((st = device_ready(&n_xcd)) != HLB_OK) return st;
+    const hipStream_t s = (hipStream_t)stream;
+    for (int l = 0; l < L; ++l) {
+        const int64_t om = (int64_t)l * m * n, ia = (int64_t)l * m * k, ix = (int64_t)l * k * n;
+        // both right operands split once, each left operand split once (run_products)
+        std::vector<RightSpec> rights{{At + ix, n, n, primes[l]}, {Bt + ix, n, n, primes[l]}};
+        std::vector<LeftSpec> lefts{{(const int64_t *)(A + ia), k, m, {C00 + om, C01 + om}, {n, n}},
+                                    {(const int64_t *)(B + ia), k, m, {C10 + om, C11 + om}, {n, n}}};
+        if ((st = run_products(pl, lefts, rights, k, n_xcd, s)) != HLB_OK) return st;
+    }
+    return HLB_OK;
+}
+
+hlb_status hlb_rescale(int64_t count, const uint64_t *X, const uint64_t *primes, int L, uint64_t *Y, void *stream) {
+    if (count < 0 || L < 2 || L > kMaxRescalePrimes || !primes) return HLB_EINVAL;
+    RescaleConsts rc;
+    std::memset(&rc, 0, sizeof(rc));
+    rc.L = L;
+    const uint64_t q = primes[L - 1];
+    for (int l = 0; l < L; ++l) {
+        if (check_modulus(primes[l]) != HLB_OK) return HLB_EINVAL;
+        rc.q[l] = primes[l];
+    }
+    for (int l = 0; l < L - 1; ++l) {
+        const uint64_t ql = primes[l];
+        rc.q_mod[l] = q % ql;
+        // q^{-1} mod ql by the extended Euclidean algorithm (signed 128-bit)
+        __int128 r0 = (__int128)ql, r1 = (__int128)(q % ql), t0 = 0, t1 = 1;
+        while (r1 != 0) {
+            const __int128 qt = r0 / r1, r2 = r0 - qt * r1, t2 = t0 - qt * t1;
+            r0 = r1;
+            r1 = r2;
+            t0 = t1;
+            t1 = t2;
+        }
+        if (r0 != 1) return HLB_EINVAL;  // not invertible
+        if (t0 < 0) t0 += ql;
+        rc.qinv[l] = (uint64_t)t0;
+        rc.qinv_shoup[l] = (uint64_t)(((unsigned __int128)rc.qinv[l] << 64) / ql);
+    }
+    if (count == 0) return HLB_OK;
+    if (!X || !Y) return HLB_EINVAL;
+    hlb_status st = device_ready(nullptr);
+    if (st != HLB_OK) return st;
+    return launch_rescale(X, count, rc, Y, (hipStream_t)stream) == hipSuccess ? HLB_OK : HLB_EDEVICE;
 }
 
 hlb_status hlb_validate_residues(const uint64_t *X, int64_t rows, int64_t cols, int64_t ld, uint64_t q,

@@ -81,6 +81,32 @@ __global__ void combine_kernel(const uint64_t *__restrict__ AS, const int64_t *_
     }
 }
 
+// Rescale by the last prime q: c = centred residue of x mod q (ties upward), then
+// y_l = (x_l - c) * q^{-1} mod q_l for l < L-1.  qinv_l = q^{-1} mod q_l with its Shoup
+// companion; all moduli < 2^52.
+__global__ void rescale_kernel(const uint64_t *__restrict__ X, int64_t count, RescaleConsts rc, uint64_t *Y) {
+    const uint64_t q = rc.q[rc.L - 1];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = X[(int64_t)(rc.L - 1) * count + i];
+        const bool up = 2 * r >= q;  // c = r - q when r/q >= 1/2 (round half up), else c = r
+        for (int l = 0; l < rc.L - 1; ++l) {
+            const uint64_t ql = rc.q[l];
+            // c mod ql: r mod ql, minus q mod ql when c = r - q
+            uint64_t cm = r % ql;
+            if (up) cm = cm >= rc.q_mod[l] ? cm - rc.q_mod[l] : cm + ql - rc.q_mod[l];
+            const uint64_t xl = X[(int64_t)l * count + i];
+            const uint64_t d = xl >= cm ? xl - cm : xl + ql - cm;
+            Y[(int64_t)l * count + i] = mulmod_shoup(d, rc.qinv[l], rc.qinv_shoup[l], ql);
+        }
+    }
+}
+
+hipError_t launch_rescale(const uint64_t *X, int64_t count, const RescaleConsts &rc, uint64_t *Y, hipStream_t s) {
+    hipLaunchKernelGGL(rescale_kernel, dim3(aux_grid(count)), dim3(kAuxThreads), 0, s, X, count, rc, Y);
+    return hipGetLastError();
+}
+
 hipError_t launch_validate(const uint64_t *X, int64_t rows, int64_t cols, int64_t ld, uint64_t q,
                            unsigned long long *first_bad, hipStream_t s) {
     hipLaunchKernelGGL(validate_kernel, dim3(aux_grid(rows * cols)), dim3(kAuxThreads), 0, s, X, rows,

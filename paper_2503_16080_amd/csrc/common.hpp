@@ -163,6 +163,16 @@ struct BatchArgs {
     int32_t nprob, kfold, group_m, n_chunks;
 };
 
+// Constants of a rescale by the last of L primes: q mod q_l and q^{-1} mod q_l (Shoup form).
+constexpr int kMaxRescalePrimes = 64;
+struct RescaleConsts {
+    int32_t L, pad;
+    uint64_t q[kMaxRescalePrimes];
+    uint64_t q_mod[kMaxRescalePrimes];
+    uint64_t qinv[kMaxRescalePrimes];
+    uint64_t qinv_shoup[kMaxRescalePrimes];
+};
+
 // Maps a workgroup id to (row tile, column tile).  Workgroups are dealt to the XCDs
 // round-robin, so ids w, w+n_xcd, ... share an XCD and its L2.  The remap gives every XCD a
 // contiguous run of logical tiles, and the raster walks group_m row tiles column by column

@@ -26,6 +26,23 @@ struct Plan {
 };
 
 hlb_status plan(int kind, int64_t k, uint64_t qmax, int64_t pmax, int form, Plan *pl);
+
+// Operands of run_products: left operands (plaintexts or residue matrices, m x k) and right
+// operands (residue matrices, k x n, each with its modulus); C[r] / ldc[r] of a left operand
+// receive its product with right operand r.
+struct LeftSpec {
+    const int64_t *P;
+    int64_t ldp, m;
+    std::vector<uint64_t *> C;
+    std::vector<int64_t> ldc;
+};
+struct RightSpec {
+    const uint64_t *X;
+    int64_t ldx, n;
+    uint64_t q;
+};
+hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, const std::vector<RightSpec> &rights,
+                        int64_t k, int n_xcd, hipStream_t s);
 // Picks the INT8 tile class of a problem (m rows, n columns per output matrix, depth k) and
 // updates pl->cls / bm / bn accordingly; no-op for plans with a single class.
 void choose_class(Plan *pl, int64_t m, int64_t n, int64_t k);

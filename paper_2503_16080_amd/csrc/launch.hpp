@@ -44,6 +44,7 @@ hipError_t launch_encode(const double *M, int64_t count, double delta, int64_t *
 // E signed: used by the test-only encrypt (sign = -1) and decrypt (sign = +1, E = residues).
 hipError_t launch_combine(const uint64_t *AS, const int64_t *Es, const uint64_t *Eu, int sign,
                           int64_t count, uint64_t q, uint64_t *out, hipStream_t s);
+hipError_t launch_rescale(const uint64_t *X, int64_t count, const RescaleConsts &rc, uint64_t *Y, hipStream_t s);
 hipError_t launch_residues_of_signed(const int64_t *v, int64_t count, uint64_t q, uint64_t *out,
                                      hipStream_t s);
 

@@ -307,3 +307,50 @@ def test_golden_regression_fixture(orc):
             q0, qL = w.primes[0], w.primes[-1]
             assert sum(int(w.P[0, l]) * int(w.A[0, l, 0]) for l in range(c["k"])) % q0 == c["corner"][0]
             assert sum(int(w.P[-1, l]) * int(w.B[-1, l, -1]) for l in range(c["k"])) % qL == c["corner"][1]
+
+
+def test_rescale_definition_pins(orc):
+    # (1) brute force with exact fractions, ties rounded upward; (2) x = q y + e recovers
+    # y + round(e / q); (3) the result does not depend on the representative of x mod Q.
+    from fractions import Fraction
+    import math
+    primes = [97, 101, 103]
+    Q = 97 * 101 * 103
+    q = 103
+    xs = [0, 1, 51, 52, 103, 154, 155, 5000, Q - 1, Q // 2, Q // 2 + 1, 206 + 51, 206 + 52]
+    X = np.array([[x % p for x in xs] for p in primes], dtype=np.uint64)
+    got = orc.rescale(X, primes)
+    for i, x in enumerate(xs):
+        xc = x - Q if x > Q // 2 else x          # the centred representative is what is lifted
+        want = math.floor(Fraction(xc, q) + Fraction(1, 2))
+        assert [int(got[l, i]) for l in range(2)] == [want % 97, want % 101]
+    primes = wl.ntt_primes(50, 3)
+    g = np.random.default_rng(17)
+    q = primes[-1]
+    y = g.integers(-(1 << 40), 1 << 40, size=50)
+    e = g.integers(-(q // 2) + 1, q // 2, size=50)
+    x = [int(a) * q + int(b) for a, b in zip(y, e)]
+    X = np.array([[v % p for v in x] for p in primes], dtype=np.uint64)
+    got = orc.rescale(X, primes)
+    for l in range(2):
+        assert got[l].tolist() == [int(a) % primes[l] for a in y]
+    # ties: e = q/2 rounds up (q odd: e = (q+1)/2 up, (q-1)/2 down)
+    x = [5 * q + (q + 1) // 2, 5 * q + (q - 1) // 2]
+    X = np.array([[v % p for v in x] for p in primes], dtype=np.uint64)
+    assert orc.rescale(X, primes)[0].tolist() == [6, 5]
+
+
+def test_ccmm_core_composes_definitions(orc):
+    primes = wl.ntt_primes(50, 2)
+    g = np.random.default_rng(18)
+    A, B = (np.stack([g.integers(0, q, size=(4, 6), dtype=np.uint64) for q in primes]) for _ in range(2))
+    At, Bt = (np.stack([g.integers(0, q, size=(6, 5), dtype=np.uint64) for q in primes]) for _ in range(2))
+    C = orc.ccmm_pp_core(A, B, At, Bt, primes)
+    for l, q in enumerate(primes):
+        top = np.concatenate([A[l], B[l]]).tolist()
+        right = np.concatenate([At[l], Bt[l]], axis=1).tolist()
+        full = _brute(q, top, right)   # [A; B] * [At Bt] as one product
+        assert C[0][l].tolist() == [r[:5] for r in full[:4]]
+        assert C[1][l].tolist() == [r[5:] for r in full[:4]]
+        assert C[2][l].tolist() == [r[:5] for r in full[4:]]
+        assert C[3][l].tolist() == [r[5:] for r in full[4:]]
