@@ -87,7 +87,9 @@ def summarize_counters(fetch_dir, write_dir, d, L):
     import statistics
 
     def per_kernel(path, counter):
-        rows = list(csv.DictReader(open(os.path.join(path, "p_counter_collection.csv"))))
+        import glob
+        (name,) = glob.glob(os.path.join(path, "*counter_collection.csv"))
+        rows = list(csv.DictReader(open(name)))
         gemm = [float(r["Counter_Value"]) for r in rows
                 if r["Counter_Name"] == counter and "gemm_i8_kernel" in r["Kernel_Name"]]
         copy = [float(r["Counter_Value"]) for r in rows
