@@ -40,9 +40,12 @@ def _parse():
     ap.add_argument("--bits", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-limb and dgemm legs")
-    ap.add_argument("--workload", choices=["cpmm", "batch"], default="cpmm",
+    ap.add_argument("--workload", choices=["cpmm", "batch", "trunc"], default="cpmm",
                     help="cpmm: one CP-MM of size --d (default); batch: 64 CP-MMs of uneven "
-                         "shapes over 4 primes of 45 bits")
+                         "shapes over 4 primes of 45 bits; trunc: the CP-MM of size --d with "
+                         "the b-part truncated (Strategy 2) next to the exact one")
+    ap.add_argument("--b-err-log2", type=float, default=45.0,
+                    help="trunc workload: error budget of the b-part (log2)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the counter summary from two rocprofv3 --pmc output directories "
                          "(FETCH_SIZE run, WRITE_SIZE run) and exit")
@@ -53,7 +56,7 @@ def _parse():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_i8_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2503_16080_amd", "csrc", f) for f in ("gemm_i8.hip", "common.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2503_16080_amd", "csrc", f) for f in ("gemm_i8.hip", "i8_tile.hpp", "common.hpp")]
 
 
 def kernel_source_hash() -> str:
@@ -191,6 +194,64 @@ def run_batch(args):
     }), flush=True)
 
 
+def run_trunc(args):
+    """CP-MM with a truncated b-part (Strategy 2 of Section 6.1) against the exact CP-MM, in
+    both limb forms, on the default workload's inputs; the FP64 form with truncation is the
+    paper's own configuration (3 limb products on the a-part, 1 on the b-part)."""
+    import numpy as np
+    import torch
+
+    import paper_2503_16080_amd as hlb
+    import workloads as wl
+
+    # Strategy 2's error argument is for one modulus (the paper's setting), so one prime
+    d, L = args.d, 1
+    w = wl.cpmm_uniform(1003, d, d, d, args.bits, L)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev)
+    P, A, B = t(w.P), t(w.A), t(w.B)
+    PA = torch.empty((L, d, d), dtype=torch.int64, device=dev)
+    PB = torch.empty((L, d, d), dtype=torch.int64, device=dev)
+    macs = 2 * L * d * d * d
+    budget = args.b_err_log2
+    res = {}
+    for form in ("int8", "fp64"):
+        steps = args.steps if form == "int8" else max(2, args.steps // 3)
+        warm = args.warmup if form == "int8" else 1
+        plan = hlb.plan_trunc_b(d, min(w.primes), max(w.primes), w.p_absmax, budget, form)
+        exact = lambda: hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form=form, out=(PA, PB))
+        trunc = lambda: hlb.cp_mm_trunc_b(P, A, B, w.primes, budget, p_absmax=w.p_absmax, form=form,
+                                          out=(PA, PB))
+        s_exact = _time_steps(exact, steps, warm)
+        hlb.profile_reset()
+        hlb.set_option(hlb.OPT_PROFILE, 1)
+        s_trunc = _time_steps(trunc, steps, warm)
+        hlb.set_option(hlb.OPT_PROFILE, 0)
+        kname = "gemm_i8_trunc" if form == "int8" else "gemm_f64_trunc"
+        n_k, ms_k = hlb.profile_read(kname)
+        hlb.profile_reset()
+        res[form] = {"exact_ms": s_exact * 1e3, "trunc_ms": s_trunc * 1e3,
+                     "trunc_value": macs / s_trunc, "exact_value": macs / s_exact,
+                     "b_part_products": plan["products"], "dropped_shifts": plan["dropped_shifts"],
+                     "b_err_bound_log2": plan["err_bound_log2"],
+                     "b_part_kernel": kname, "b_part_kernel_ms": ms_k / max(n_k, 1)}
+    Xf = torch.rand((d, d), dtype=torch.float64, device=dev)
+    Yf = torch.rand((d, d), dtype=torch.float64, device=dev)
+    Zf = torch.empty((d, d), dtype=torch.float64, device=dev)
+    s_dgemm = _time_steps(lambda: torch.matmul(Xf, Yf, out=Zf), max(3, args.steps // 2), 2)
+    for form in res:
+        res[form]["slowdown_vs_fp64_gemm"] = res[form]["trunc_ms"] / (s_dgemm * 1e3)
+    print(json.dumps({
+        "metric": f"CP-MM mod-q MACs/s at d={d} with the b-part truncated (Strategy 2)",
+        "value": res["int8"]["trunc_value"], "unit": "mod-q MAC/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["int8"]["trunc_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+        "config": {"workload": f"cp_mm d={d} over one modulus of {args.bits} bits, a-part exact, "
+                               f"b-part error <= 2^{budget:g}", "b_err_log2": budget},
+        "forms": res, "fp64_gemm_ms": s_dgemm * 1e3,
+    }), flush=True)
+
+
 def main():
     args = _parse()
     if args.summarize_counters:
@@ -217,6 +278,9 @@ def main():
 
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "trunc":
+        run_trunc(args)
         return
 
     d, L = args.d, args.primes

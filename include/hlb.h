@@ -90,6 +90,43 @@ hlb_status hlb_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB,
                      uint64_t *PA, uint64_t *PB, int form, void *stream);
 
 /*
+ * CP-MM with an approximate b-part (Strategy 2 of Section 6.1, "truncation") over ONE
+ * modulus q = primes[0] (L must be 1): PA = P * A mod q exactly, as in hlb_cp_mm, and every
+ * entry of PB equals the exact residue plus an integer e with |e| <= 2^b_err_log2
+ * (PB = P * B + e mod q).  An error on the b-part reaches the decrypted message
+ * unamplified (Section 6.1).  The method's error argument holds for a single modulus, the
+ * paper's setting of one word-size q: over an RNS basis each prime's product would carry a
+ * different error, and the CRT lift of such residues is not close to the exact product, so
+ * L > 1 is rejected (HLB_EINVAL).  Other arguments as for hlb_cp_mm.
+ *
+ * The library takes the cheapest b-part plan of `form` whose worst-case error bound is at
+ * most 2^b_err_log2 and below q / 2; the exact plan always qualifies:
+ *   INT8: the digit products P_i B_j of the shifts i + j < drop (drop <= 3) are skipped:
+ *         |e| <= k * 2^14 * sum_{s < drop} pairs(s) * 256^s, with pairs(s) the number of
+ *         digit pairs of shift s.  Only when k needs no K fold (k <= 43690).
+ *   FP64: one FP64 product of P and B rounded to doubles (B in its centred representative
+ *         in (-q/2, q/2]), reduced mod q: |e| <= (k + 2) 2^-52 * k * p_absmax * (q/2)
+ *         (zero when k * p_absmax * (q/2) < 2^53).  Needs k * p_absmax <= 2^51.
+ * hlb_plan_trunc_b reports the choice.  The two parts are computed in separate launches.
+ */
+hlb_status hlb_cp_mm_trunc_b(int64_t m, int64_t k, int64_t nA, int64_t nB,
+                             const int64_t *P, int64_t ldp, int64_t p_absmax,
+                             const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L,
+                             uint64_t *PA, uint64_t *PB, double b_err_log2, int form, void *stream);
+
+/* The b-part plan hlb_cp_mm_trunc_b takes for depth k, moduli in [q_min, q_max], |P| <=
+ * p_absmax (>= 1) and budget b_err_log2. */
+typedef struct {
+    int form;             /* HLB_FORM_INT8 or HLB_FORM_FP64 */
+    int truncated;        /* 0: the exact plan */
+    int dropped_shifts;   /* INT8: shifts whose digit products are skipped */
+    int products;         /* limb products per mod-q MAC of the b-part */
+    double err_bound_log2;/* log2 of the worst-case |e|; -inf when exact */
+} hlb_trunc_desc;
+hlb_status hlb_plan_trunc_b(int64_t k, uint64_t q_min, uint64_t q_max, int64_t p_absmax,
+                            double b_err_log2, int form, hlb_trunc_desc *out);
+
+/*
  * The plaintext-product core of the ciphertext-ciphertext product (Algorithm alg:ccmm, step
  * 2): for every prime l < L, the four Mod-PP-MMs
  *     C00[l] = A[l] At[l],  C01[l] = A[l] Bt[l],  C10[l] = B[l] At[l],  C11[l] = B[l] Bt[l]

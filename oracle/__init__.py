@@ -14,6 +14,11 @@ Contents
 * CKKS helpers written from Section 2.2 (coefficient encoding, Dec) and the row-encryption
   identity A * S + B = Delta * M (mod q) (Eq mat_row_format): ``encode``, ``encrypt``,
   ``decrypt``, ``crt_lift_centered``, ``decode``, ``precision_bits``.
+* ``rescale`` (Section 2.2) and ``ccmm_pp_core`` (Algorithm alg:ccmm's plaintext products).
+* Strategy 2 of Section 6.1 (truncation), the approximate Mod-PP-MM for the b-part:
+  ``mod_pp_mm_drop_i8`` keeps only the digit products of the high shifts (base 256, the
+  compromise between Strategies 1 and 2 the paper mentions) and ``mod_pp_mm_trunc_fp64``
+  is one floating-point product of the operands rounded to doubles (K = 2^53).
 """
 from __future__ import annotations
 
@@ -266,3 +271,56 @@ def ccmm_pp_core(A, B, At, Bt, primes):
         out[2].append(mod_pp_mm(q, B[l], At[l]))
         out[3].append(mod_pp_mm(q, B[l], Bt[l]))
     return tuple(np.stack(o) for o in out)
+
+
+def balanced_digits(v, D: int):
+    """The D digits d_0 .. d_{D-1} in [-128, 127] with sum_j d_j 256^j = v (the decomposition
+    of Eq decomp with K = 256, digits of either sign).  v: integer array with |v| < 2^62;
+    raises ValueError when v needs more than D digits."""
+    v = np.asarray(v, dtype=np.int64).copy()
+    digits = []
+    for _ in range(D):
+        d = (v + 128) % 256 - 128          # numpy integer % is a floor modulo
+        digits.append(d)
+        v = (v - d) // 256                 # exact: v - d is a multiple of 256
+    if np.any(v != 0):
+        raise ValueError(f"value needs more than {D} balanced base-256 digits")
+    return digits
+
+
+def mod_pp_mm_drop_i8(q: int, P, X, drop: int, dp: int, dx: int) -> np.ndarray:
+    """Truncated Mod-PP-MM in base 256: with P = sum_i P_i 256^i (dp signed digits of the
+    signed plaintext) and X = sum_j X_j 256^j (dx digits of the residues), the integer
+    sum over i + j >= drop of (P_i X_j) 256^(i+j), reduced mod q -- Strategy 2 of Section
+    6.1 keeping only the terms of the decomposition above shift `drop`."""
+    q = int(q)
+    Pd = balanced_digits(P, dp)
+    Xd = balanced_digits(np.asarray(X, dtype=np.uint64).astype(np.int64), dx)
+    total = np.zeros((np.shape(P)[0], np.shape(X)[1]), dtype=object)
+    for i in range(dp):
+        for j in range(dx):
+            if i + j >= drop:
+                # each entry is a sum of k products of two digits: |.| <= k 2^14, exact in int64
+                total = total + (Pd[i] @ Xd[j]).astype(object) * (256 ** (i + j))
+    return np.array([[int(t) % q for t in row] for row in total], dtype=np.uint64)
+
+
+def centred(X, q: int) -> np.ndarray:
+    """Centred representatives in (-q/2, q/2] of residues X in [0, q)."""
+    X = np.asarray(X, dtype=np.uint64).astype(np.int64)
+    return np.where(2 * X > int(q), X - int(q), X)
+
+
+def mod_pp_mm_trunc_fp64(q: int, P, X) -> np.ndarray:
+    """Strategy 2 of Section 6.1 with K = 2^53: round both operands to doubles (the signed
+    plaintext P, the residues X in their centred representatives), multiply them with one
+    floating-point matrix product, and return the canonical residue mod q of the result.
+    The product's entries are integer-valued doubles (every rounding of an integer of
+    magnitude >= 2^53 is again an integer), so the residue is well defined."""
+    q = int(q)
+    Pt = np.asarray(P, dtype=np.int64).astype(np.float64)
+    Xt = centred(X, q).astype(np.float64)
+    Y = Pt @ Xt
+    if not np.all(np.isfinite(Y)) or not np.all(Y == np.floor(Y)):
+        raise ValueError("floating-point product is not integer-valued")
+    return np.array([[int(y) % q for y in row] for row in Y.tolist()], dtype=np.uint64)

@@ -57,6 +57,11 @@ class PlanDesc(ctypes.Structure):
                 ("k_chunk", ctypes.c_int64), ("acc_bound_log2", ctypes.c_double)]
 
 
+class TruncDesc(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int), ("truncated", ctypes.c_int), ("dropped_shifts", ctypes.c_int),
+                ("products", ctypes.c_int), ("err_bound_log2", ctypes.c_double)]
+
+
 class CpmmProblem(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("k", ctypes.c_int64), ("nA", ctypes.c_int64),
                 ("nB", ctypes.c_int64), ("P", ctypes.c_void_p), ("ldp", ctypes.c_int64),
@@ -81,6 +86,9 @@ def load():
             "hlb_status_str": (ctypes.c_char_p, [ci]),
             "hlb_mod_pp_mm": (ci, [u64, i64, i64, i64, vp, i64, vp, i64, vp, i64, ci, vp]),
             "hlb_cp_mm": (ci, [i64, i64, i64, i64, vp, i64, i64, vp, vp, vp, ci, vp, vp, ci, vp]),
+            "hlb_cp_mm_trunc_b": (ci, [i64, i64, i64, i64, vp, i64, i64, vp, vp, vp, ci, vp, vp,
+                                       ctypes.c_double, ci, vp]),
+            "hlb_plan_trunc_b": (ci, [i64, u64, u64, i64, ctypes.c_double, ci, vp]),
             "hlb_cp_mm_batch": (ci, [vp, ci, vp, ci, ci, vp]),
             "hlb_validate_residues": (ci, [vp, i64, i64, i64, u64, vp, vp]),
             "hlb_plaintext_absmax": (ci, [vp, i64, i64, i64, vp, vp]),
@@ -162,13 +170,7 @@ def hlb_mod_pp_mm(q: int, P: torch.Tensor, X: torch.Tensor, form="auto", out=Non
     return C
 
 
-def hlb_cp_mm(P: torch.Tensor, A: torch.Tensor, B: torch.Tensor, primes: Sequence[int],
-              p_absmax: int = 0, form="int8", out=None, stream=None):
-    """(P A_l mod q_l, P B_l mod q_l) for every prime (CP-MM over an RNS basis).
-
-    P: m x k signed int64; A: [L, k, nA], B: [L, k, nB] residues (contiguous).  Returns
-    (PA, PB) of shapes [L, m, nA], [L, m, nB].  p_absmax = 0 measures max |P| on the device.
-    """
+def _cp_mm_operands(P, A, B, primes, out):
     _dev64(P, "P")
     _dev64(A, "A")
     _dev64(B, "B")
@@ -188,10 +190,39 @@ def hlb_cp_mm(P: torch.Tensor, A: torch.Tensor, B: torch.Tensor, primes: Sequenc
         if not (PA.is_contiguous() and PB.is_contiguous()):
             raise ValueError("outputs must be contiguous")
     qs = (ctypes.c_uint64 * max(L, 1))(*[int(q) for q in primes])
-    _check(load().hlb_cp_mm(m, k, nA, nB, P.data_ptr(), _row_stride(P, "P"), int(p_absmax),
-                            A.data_ptr(), B.data_ptr(), qs, L, PA.data_ptr(), PB.data_ptr(),
-                            _form(form), _stream(stream)), "cp_mm")
+    return (m, k, nA, nB, P.data_ptr(), _row_stride(P, "P")), (A.data_ptr(), B.data_ptr(), qs, L,
+                                                              PA.data_ptr(), PB.data_ptr()), PA, PB
+
+
+def hlb_cp_mm(P: torch.Tensor, A: torch.Tensor, B: torch.Tensor, primes: Sequence[int],
+              p_absmax: int = 0, form="int8", out=None, stream=None):
+    """(P A_l mod q_l, P B_l mod q_l) for every prime (CP-MM over an RNS basis).
+
+    P: m x k signed int64; A: [L, k, nA], B: [L, k, nB] residues (contiguous).  Returns
+    (PA, PB) of shapes [L, m, nA], [L, m, nB].  p_absmax = 0 measures max |P| on the device.
+    """
+    head, tail, PA, PB = _cp_mm_operands(P, A, B, primes, out)
+    _check(load().hlb_cp_mm(*head, int(p_absmax), *tail, _form(form), _stream(stream)), "cp_mm")
     return PA, PB
+
+
+def hlb_cp_mm_trunc_b(P: torch.Tensor, A: torch.Tensor, B: torch.Tensor, primes: Sequence[int],
+                      b_err_log2: float, p_absmax: int = 0, form="int8", out=None, stream=None):
+    """CP-MM with the a-part exact and the b-part within 2^b_err_log2 of the exact residue
+    (Strategy 2 of Section 6.1); arguments and results as for hlb_cp_mm."""
+    head, tail, PA, PB = _cp_mm_operands(P, A, B, primes, out)
+    _check(load().hlb_cp_mm_trunc_b(*head, int(p_absmax), *tail, float(b_err_log2), _form(form),
+                                    _stream(stream)), "cp_mm_trunc_b")
+    return PA, PB
+
+
+def hlb_plan_trunc_b(k: int, q_min: int, q_max: int, p_absmax: int, b_err_log2: float,
+                     form="int8") -> dict:
+    """The b-part plan hlb_cp_mm_trunc_b would take (host only)."""
+    d = TruncDesc()
+    _check(load().hlb_plan_trunc_b(int(k), int(q_min), int(q_max), int(p_absmax),
+                                   float(b_err_log2), _form(form), ctypes.byref(d)), "plan_trunc_b")
+    return {f: getattr(d, f) for f, _ in TruncDesc._fields_}
 
 
 def hlb_cp_mm_batch(problems, primes: Sequence[int], form="int8", stream=None):
@@ -357,6 +388,8 @@ ccmm_pp_core = hlb_ccmm_pp_core
 rescale = hlb_rescale
 mod_pp_mm = hlb_mod_pp_mm
 cp_mm = hlb_cp_mm
+cp_mm_trunc_b = hlb_cp_mm_trunc_b
+plan_trunc_b = hlb_plan_trunc_b
 cp_mm_batch = hlb_cp_mm_batch
 validate_residues = hlb_validate_residues
 plaintext_absmax = hlb_plaintext_absmax

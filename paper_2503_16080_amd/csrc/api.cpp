@@ -205,6 +205,56 @@ hlb_status plan_f64(int kind, int64_t k, uint64_t qmax, int64_t pmax, Plan *pl) 
     return HLB_EBOUND;
 }
 
+// Truncated b-part plans (Strategy 2 of Section 6.1).
+//  INT8: skipping the products P_i X_j with i + j < drop changes the integer result by
+//        D = sum_{i+j<drop} (P_i X_j) 256^(i+j) with |P_i X_j| <= k * 2^14 per entry, so
+//        |D| <= k 2^14 sum_{s<drop} pairs(s) 256^s.  Only without a K fold (k <= kchunk).
+//  FP64: one product of the rounded operands; |P| <= pmax and |centred X| <= q/2, so each of
+//        the k terms is at most pmax q/2 and any summation order with faithfully rounded
+//        operations is within (k + 2) 2^-52 sum |terms| of the exact value.  The result is
+//        exact when every partial sum stays below 2^53.  The epilogue needs |acc| < q 2^51,
+//        which k * pmax <= 2^51 guarantees.
+hlb_status plan_trunc_b(int64_t k, uint64_t qmin, uint64_t qmax, int64_t pmax, double err_log2, int form, Plan *pl) {
+    hlb_status st = plan(1, k, qmax, pmax, form, pl);
+    if (st != HLB_OK) return st;
+    const double half_qmin = std::log2((double)qmin) - 1.0;
+    const double kk = (double)std::max<int64_t>(k, 1);
+    if (pl->form == HLB_FORM_INT8) {
+        if (pl->np != 3 || k > pl->kchunk) return HLB_OK;
+        for (int drop = 3; drop >= 1; --drop) {
+            double sum = 0.0;
+            for (int s = 0; s < drop; ++s) {
+                int pairs = 0;
+                for (int i = 0; i < pl->np; ++i)
+                    if (s - i >= 0 && s - i < pl->nx) ++pairs;
+                sum += pairs * std::ldexp(1.0, 8 * s);
+            }
+            const double bound = std::log2(kk * 16384.0 * sum);
+            if (bound <= err_log2 && bound < half_qmin) {
+                pl->drop = drop;
+                pl->err_bound_log2 = bound;
+                return HLB_OK;
+            }
+        }
+        return HLB_OK;
+    }
+    // FP64
+    const double terms = kk * (double)std::max<int64_t>(pmax, 1) * (double)(qmax / 2);
+    if (kk * (double)std::max<int64_t>(pmax, 1) > std::ldexp(1.0, 51)) return HLB_OK;
+    const double bound = terms < std::ldexp(1.0, 53) ? -__builtin_inf() : std::log2((kk + 2.0) * std::ldexp(terms, -52));
+    if (bound <= err_log2 && bound < half_qmin) {
+        pl->trunc = true;
+        pl->np = 1;
+        pl->nx = 1;
+        pl->limb_bits = 0;
+        pl->pairs = 1;
+        pl->kchunk = INT64_MAX / 2;
+        pl->acc_bound_log2 = std::log2(std::max(terms, 1.0));
+        pl->err_bound_log2 = bound;
+    }
+    return HLB_OK;
+}
+
 hlb_status plan(int kind, int64_t k, uint64_t qmax, int64_t pmax, int form, Plan *pl) {
     if (form == HLB_FORM_INT8) return plan_i8(kind, k, qmax, pmax, pl);
     if (form == HLB_FORM_FP64) return plan_f64(kind, k, qmax, pmax, pl);
@@ -403,9 +453,15 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
             tile_base += tb;
             if (tb == 0) continue;
             hipError_t e;
-            if (pl.form == HLB_FORM_INT8) {
+            if (pl.form == HLB_FORM_INT8 && pl.drop > 0) {
+                ProfScope ps("gemm_i8_trunc", s);
+                e = launch_gemm_i8_trunc(pl.np, pl.nx, pl.cls, pl.drop, a, s);
+            } else if (pl.form == HLB_FORM_INT8) {
                 ProfScope ps("gemm_i8", s);
                 e = launch_gemm_i8(pl.np, pl.nx, pl.cls, a, s);
+            } else if (pl.trunc) {
+                ProfScope ps("gemm_f64_trunc", s);
+                e = launch_gemm_f64_trunc(a, s);
             } else {
                 ProfScope ps("gemm_f64", s);
                 e = launch_gemm_f64(pl.np, pl.nx, a, s);
@@ -432,6 +488,38 @@ hlb_status measure_absmax(const int64_t *P, int64_t m, int64_t k, int64_t ld, in
     if (hipStreamSynchronize(s) != hipSuccess) st = HLB_EDEVICE;
     if (st == HLB_OK) *out = h > (unsigned long long)INT64_MAX ? INT64_MAX : (int64_t)h;
     return st;
+}
+
+// Shared argument checks and plaintext bound of the CP-MM entry points.
+static hlb_status cp_mm_prepare(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp,
+                                int64_t *p_absmax, const uint64_t *A, const uint64_t *B, const uint64_t *primes,
+                                int L, uint64_t *PA, uint64_t *PB, hipStream_t s, uint64_t *qmin, uint64_t *qmax,
+                                int *n_xcd, bool *nothing) {
+    *nothing = false;
+    if (m < 0 || k < 0 || nA < 0 || nB < 0 || L < 0 || L > 1024 || *p_absmax < 0 ||
+        (uint64_t)*p_absmax >= kMaxModulus)
+        return HLB_EINVAL;
+    if (L == 0 || m == 0 || (nA == 0 && nB == 0)) {
+        *nothing = true;
+        return HLB_OK;
+    }
+    if (!primes) return HLB_EINVAL;
+    *qmin = UINT64_MAX;
+    *qmax = 0;
+    for (int l = 0; l < L; ++l) {
+        if (check_modulus(primes[l]) != HLB_OK) return HLB_EINVAL;
+        *qmax = std::max(*qmax, primes[l]);
+        *qmin = std::min(*qmin, primes[l]);
+    }
+    if ((nA > 0 && !PA) || (nB > 0 && !PB)) return HLB_EINVAL;
+    if (k > 0 && (!P || ldp < k || (nA > 0 && !A) || (nB > 0 && !B))) return HLB_EINVAL;
+    hlb_status st = device_ready(n_xcd);
+    if (st != HLB_OK) return st;
+    if (*p_absmax == 0 && k > 0) {
+        if ((st = measure_absmax(P, m, k, ldp, p_absmax, s)) != HLB_OK) return st;
+        if ((uint64_t)*p_absmax >= kMaxModulus) return HLB_ERANGE;
+    }
+    return HLB_OK;
 }
 
 }  // namespace hlb
@@ -492,26 +580,13 @@ hlb_status hlb_mod_pp_mm(uint64_t q, int64_t m, int64_t k, int64_t n, const uint
 hlb_status hlb_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp,
                      int64_t p_absmax, const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L,
                      uint64_t *PA, uint64_t *PB, int form, void *stream) {
-    if (m < 0 || k < 0 || nA < 0 || nB < 0 || L < 0 || L > 1024 || p_absmax < 0 ||
-        (uint64_t)p_absmax >= kMaxModulus)
-        return HLB_EINVAL;
-    if (L == 0 || m == 0 || (nA == 0 && nB == 0)) return HLB_OK;
-    if (!primes) return HLB_EINVAL;
-    uint64_t qmax = 0;
-    for (int l = 0; l < L; ++l) {
-        if (check_modulus(primes[l]) != HLB_OK) return HLB_EINVAL;
-        qmax = std::max(qmax, primes[l]);
-    }
-    if ((nA > 0 && !PA) || (nB > 0 && !PB)) return HLB_EINVAL;
-    if (k > 0 && (!P || ldp < k || (nA > 0 && !A) || (nB > 0 && !B))) return HLB_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
+    const hipStream_t s = (hipStream_t)stream;
+    uint64_t qmin = 0, qmax = 0;
     int n_xcd = 8;
-    hlb_status st = device_ready(&n_xcd);
-    if (st != HLB_OK) return st;
-    if (p_absmax == 0 && k > 0) {
-        if ((st = measure_absmax(P, m, k, ldp, &p_absmax, s)) != HLB_OK) return st;
-        if ((uint64_t)p_absmax >= kMaxModulus) return HLB_ERANGE;
-    }
+    bool nothing = false;
+    hlb_status st = cp_mm_prepare(m, k, nA, nB, P, ldp, &p_absmax, A, B, primes, L, PA, PB, s, &qmin, &qmax,
+                                  &n_xcd, &nothing);
+    if (st != HLB_OK || nothing) return st;
     Plan pl;
     if ((st = plan(1, k, qmax, std::max<int64_t>(p_absmax, 1), form, &pl)) != HLB_OK) return st;
     choose_class(&pl, m, std::max(nA, nB), k);
@@ -530,6 +605,72 @@ hlb_status hlb_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t
         }
     }
     return run_products(pl, {left}, rights, k, n_xcd, s);
+}
+
+hlb_status hlb_plan_trunc_b(int64_t k, uint64_t q_min, uint64_t q_max, int64_t p_absmax, double b_err_log2,
+                            int form, hlb_trunc_desc *out) {
+    if (!out || k < 0 || check_modulus(q_min) != HLB_OK || check_modulus(q_max) != HLB_OK || q_min > q_max ||
+        p_absmax < 1 || (uint64_t)p_absmax >= kMaxModulus)
+        return HLB_EINVAL;
+    Plan pl;
+    const hlb_status st = plan_trunc_b(k, q_min, q_max, p_absmax, b_err_log2, form, &pl);
+    if (st != HLB_OK) return st;
+    out->form = pl.form;
+    out->truncated = pl.drop > 0 || pl.trunc;
+    out->dropped_shifts = pl.drop;
+    int products = pl.np * pl.nx;
+    for (int i = 0; i < pl.np; ++i)
+        for (int j = 0; j < pl.nx; ++j)
+            if (i + j < pl.drop) --products;
+    out->products = products;
+    out->err_bound_log2 = pl.err_bound_log2;
+    return HLB_OK;
+}
+
+hlb_status hlb_cp_mm_trunc_b(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp,
+                             int64_t p_absmax, const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L,
+                             uint64_t *PA, uint64_t *PB, double b_err_log2, int form, void *stream) {
+    const hipStream_t s = (hipStream_t)stream;
+    uint64_t qmin = 0, qmax = 0;
+    int n_xcd = 8;
+    bool nothing = false;
+    // one modulus only: over an RNS basis every prime's product would carry its own error,
+    // and the CRT lift of such residues is not close to the exact product
+    if (L > 1) return HLB_EINVAL;
+    hlb_status st = cp_mm_prepare(m, k, nA, nB, P, ldp, &p_absmax, A, B, primes, L, PA, PB, s, &qmin, &qmax,
+                                  &n_xcd, &nothing);
+    if (st != HLB_OK || nothing) return st;
+    const int64_t pmax = std::max<int64_t>(p_absmax, 1);
+    Plan pa, pb;
+    if ((st = plan(1, k, qmax, pmax, form, &pa)) != HLB_OK) return st;
+    if ((st = plan_trunc_b(k, qmin, qmax, pmax, b_err_log2, form, &pb)) != HLB_OK) return st;
+    choose_class(&pa, m, std::max(nA, nB), k);
+    choose_class(&pb, m, std::max(nA, nB), k);
+    LeftSpec la{P, ldp, m, {}, {}}, lb{P, ldp, m, {}, {}};
+    std::vector<RightSpec> ra, rb;
+    for (int l = 0; l < L; ++l) {
+        if (nA > 0) {
+            ra.push_back({A + (int64_t)l * k * nA, nA, nA, primes[l]});
+            la.C.push_back(PA + (int64_t)l * m * nA);
+            la.ldc.push_back(nA);
+        }
+        if (nB > 0) {
+            rb.push_back({B + (int64_t)l * k * nB, nB, nB, primes[l]});
+            lb.C.push_back(PB + (int64_t)l * m * nB);
+            lb.ldc.push_back(nB);
+        }
+    }
+    if (!pb.trunc && pb.drop == 0) {
+        // nothing truncated: the exact CP-MM in one launch
+        for (size_t i = 0; i < rb.size(); ++i) {
+            ra.push_back(rb[i]);
+            la.C.push_back(lb.C[i]);
+            la.ldc.push_back(lb.ldc[i]);
+        }
+        return run_products(pa, {la}, ra, k, n_xcd, s);
+    }
+    if ((st = run_products(pa, {la}, ra, k, n_xcd, s)) != HLB_OK) return st;
+    return run_products(pb, {lb}, rb, k, n_xcd, s);
 }
 
 hlb_status hlb_ccmm_pp_core(int64_t m, int64_t k, int64_t n, const uint64_t *A, const uint64_t *B,

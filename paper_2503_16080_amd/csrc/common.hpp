@@ -57,11 +57,14 @@ __device__ __forceinline__ uint64_t reduce_near(int64_t t, uint64_t q, double qi
     return (uint64_t)r;
 }
 
-// Canonical c mod q for an integer-valued double |c| < 2^53.  The estimate c * (1/q) has
-// absolute error <= |c/q| * 2^-52 < 2/q <= 1, so est = floor(.) is off by at most two and
-// the exact remainder c - est * q lies in (-2q, 3q); for q >= 2^51 the error is < 2^-50 and
-// it lies in [-q, 2q).  Either way it is an integer below 2^53 in magnitude, so the fused
-// multiply-add that forms it rounds nothing, and two corrections each way finish.
+// Canonical c mod q for an integer-valued double c.  The estimate est = floor(c * (1/q))
+// carries two roundings (relative error <= 2^-52), so est is within |c/q| 2^-52 + 1 of c/q:
+//  * |c| < 2^53: est is off by at most two and the exact remainder c - est * q lies in
+//    (-2q, 3q); for q >= 2^51 the error is < 2^-50 and it lies in [-q, 2q);
+//  * |c| < q 2^51 (any magnitude of c/q up to 2^51): est is off by at most one and the
+//    remainder lies in [-q, 2q).
+// Either way it is an integer below 2^53 in magnitude, so the fused multiply-add that forms
+// it rounds nothing, and two corrections each way finish.
 __device__ __forceinline__ uint64_t reduce_fp(double c, uint64_t q, double qd, double qinv) {
     const double est = __builtin_floor(c * qinv);
     double r = __builtin_fma(-est, qd, c);

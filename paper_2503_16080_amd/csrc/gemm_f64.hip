@@ -11,6 +11,11 @@
 // pairs * kchunk * max|P_i| * max|X_j| < 2^53, folding longer K into 64-bit residues.
 //
 // No workspace: the limb split happens on the way from global memory into LDS.
+//
+// TRUNC = true is Strategy 2 of Section 6.1 instead: one FP64 product of the operands
+// rounded to doubles (the plaintext as a signed integer, the residues in their centred
+// representatives in (-q/2, q/2]), whose integer-valued result is then reduced modulo q.
+// Not exact: the accumulation rounds once the partial sums pass 2^53.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -27,8 +32,9 @@ struct F64Tile {
     static constexpr int STAGE = P_ELEMS + X_ELEMS;
 };
 
-template <class T, bool FOLD>
+template <class T, bool FOLD, bool TRUNC = false>
 __global__ __launch_bounds__(kThreads, 1) void gemm_f64_kernel(const GemmArgs args) {
+    static_assert(!TRUNC || (T::NP == 1 && T::NX == 1 && !FOLD), "truncation: one limb each, no fold");
     __shared__ __attribute__((aligned(16))) double lds[2 * T::STAGE];
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -112,6 +118,17 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f64_kernel(const GemmArgs ar
                 for (int i = 0; i < T::NP; ++i)
                     lp[(i * T::BK + pk + e) * T::BM + pr] = sgn * (double)((mag >> (w * i)) & mask);
             }
+        }
+        if constexpr (TRUNC) {
+            // centred representative: x - q when 2x > q
+            double c[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                c[e] = (double)(2 * rx[e] > q ? (int64_t)rx[e] - (int64_t)q : (int64_t)rx[e]);
+            double2 *dst = (double2 *)(lx + xk * T::BN + xn);
+            dst[0] = double2{c[0], c[1]};
+            dst[1] = double2{c[2], c[3]};
+            return;
         }
 #pragma unroll
         for (int j = 0; j < T::NX; ++j) {
@@ -202,7 +219,9 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f64_kernel(const GemmArgs ar
                 // 16x16 FP64 accumulator layout: column = lane % 16, row = 4 i + lane / 16
                 const int64_t row = m0 + wm * 32 + a * 16 + 4 * i + (lane >> 4);
                 const int64_t col = n0 + wn * 32 + b * 16 + (lane & 15);
-                uint64_t v = recombine(a, b, i);
+                uint64_t v;
+                if constexpr (TRUNC) v = reduce_fp(acc[a][b][0][i], q, qd, qinv);  // |acc| < q 2^51
+                else v = recombine(a, b, i);
                 if constexpr (FOLD) v = addmod(v, part[a][b][i], q);
                 if (row < args.m && col < sg.n) sg.C[row * sg.ldc + col] = v;
             }
@@ -223,6 +242,14 @@ static hipError_t launch_fold(const GemmArgs &a, hipStream_t s) {
 
 bool f64_supported(int np, int nx) {
     return (np == 1 && (nx == 3 || nx == 4)) || (np == 3 && nx == 3) || (np == 4 && nx == 4);
+}
+
+hipError_t launch_gemm_f64_trunc(const GemmArgs &a, hipStream_t s) {
+    const int grid = a.tiles_m * a.tiles_n;
+    if (grid <= 0) return hipSuccess;
+    if (a.kfold < a.kblocks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_f64_kernel<F64Tile<1, 1>, false, true>), dim3(grid), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_gemm_f64(int np, int nx, const GemmArgs &a, hipStream_t s) {

@@ -23,7 +23,15 @@ struct Plan {
     int bm = 0, bn = 0, bk = 0;
     int cls = 0;            // INT8 tile class (0: 128 x 64, 1: 64 x 128)
     double acc_bound_log2 = 0.0;
+    // Truncated plans (Strategy 2 of Section 6.1), only for the b-part of a CP-MM:
+    int drop = 0;           // INT8: digit products of shifts < drop are skipped
+    bool trunc = false;     // FP64: one product of the rounded operands
+    double err_bound_log2 = -__builtin_inf();  // worst-case |result - exact| (centred), log2
 };
+
+// Cheapest b-part plan in `form` whose worst-case error is at most 2^err_log2 (and below
+// q_min / 2); the exact plan always qualifies.
+hlb_status plan_trunc_b(int64_t k, uint64_t qmin, uint64_t qmax, int64_t pmax, double err_log2, int form, Plan *pl);
 
 hlb_status plan(int kind, int64_t k, uint64_t qmax, int64_t pmax, int form, Plan *pl);
 

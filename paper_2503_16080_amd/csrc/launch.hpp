@@ -23,6 +23,8 @@ hipError_t launch_split_rows_i8(int D, int R, const int64_t *P, int64_t ldp, int
 hipError_t launch_split_cols_i8(int D, int R, const uint64_t *X, int64_t ldx, int64_t k, int64_t n,
                                 int tiles, int kblocks, int8_t *out, hipStream_t s);
 hipError_t launch_gemm_i8(int dp, int dx, int cls, const GemmArgs &a, hipStream_t s);
+// Same tile with the digit products of shifts below `drop` (1..3) skipped; no K fold.
+hipError_t launch_gemm_i8_trunc(int dp, int dx, int cls, int drop, const GemmArgs &a, hipStream_t s);
 // Batch path: all splits of a batch in one launch, the work counter reset, and the
 // persistent GEMM over every tile of every problem.
 hipError_t launch_split_batch_i8(int D, const SplitJob *jobs, const int32_t *wg_job, int64_t total_wgs,
@@ -33,6 +35,8 @@ hipError_t launch_gemm_i8_batch(int dp, int dx, bool fold, const BatchArgs &a, i
 // FP64 form: limb counts of each operand; returns false when no instantiation exists.
 bool f64_supported(int np, int nx);
 hipError_t launch_gemm_f64(int np, int nx, const GemmArgs &a, hipStream_t s);
+// One FP64 product of the rounded operands (plaintext signed, residues centred), reduced mod q.
+hipError_t launch_gemm_f64_trunc(const GemmArgs &a, hipStream_t s);
 
 // Auxiliary kernels.
 hipError_t launch_validate(const uint64_t *X, int64_t rows, int64_t cols, int64_t ld, uint64_t q,

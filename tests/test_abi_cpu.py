@@ -124,6 +124,12 @@ def test_entry_points_reject_bad_arguments_before_device_work():
     assert lib.hlb_cp_mm(4, 4, 4, 4, fake, 4, 8, fake, fake, qs, 1, None, fake, 2, None) == 1
     assert lib.hlb_cp_mm_batch(None, 3, qs, 1, 2, None) == 1
     assert lib.hlb_cp_mm_batch(None, 0, qs, 1, 2, None) == 0
+    assert lib.hlb_cp_mm_trunc_b(4, 4, 4, 4, fake, 4, -1, fake, fake, qs, 1, fake, fake, 40.0, 2, None) == 1
+    qs2 = (ctypes.c_uint64 * 2)(Q50, Q50 - 2)
+    assert lib.hlb_cp_mm_trunc_b(4, 4, 4, 4, fake, 4, 8, fake, fake, qs2, 2, fake, fake, 40.0, 2, None) == 1
+    assert lib.hlb_cp_mm_trunc_b(4, 4, 4, 4, fake, 2, 8, fake, fake, qs, 1, fake, fake, 40.0, 2, None) == 1
+    assert lib.hlb_cp_mm_trunc_b(4, 4, 4, 4, fake, 4, 8, fake, fake, qs, 0, fake, fake, 40.0, 2, None) == 0
+    assert lib.hlb_cp_mm_trunc_b(4, 4, 4, 4, fake, 4, 8, fake, fake, qs, 1, fake, None, 40.0, 2, None) == 1
     bad = ctypes.c_int64(0)
     assert lib.hlb_validate_residues(fake, 4, 4, 3, 97, ctypes.byref(bad), None) == 1
     assert lib.hlb_validate_residues(fake, 0, 4, 4, 97, ctypes.byref(bad), None) == 0
@@ -172,3 +178,33 @@ def test_tile_class_heuristic_and_tuning_table(tmp_path):
         hlb.set_option(hlb.OPT_FORCE_CLASS, -1)
     with pytest.raises(hlb.HlbError):
         hlb.set_option(hlb.OPT_FORCE_CLASS, 2)
+
+
+def test_trunc_b_planner_bounds():
+    # INT8: the largest number of dropped shifts (<= 3) whose bound
+    # k 2^14 sum_{s<drop} pairs(s) 256^s fits the budget and stays below q_min / 2
+    import math
+    pairs = lambda s, dp, dx: sum(1 for i in range(dp) if 0 <= s - i < dx)
+    for k, bits, dx in ((8192, 50, 7), (4096, 45, 6), (300, 50, 7)):
+        q = wl.ntt_primes(bits, 1)[0]
+        for budget in (20.0, 27.5, 36.5, 40.0, 45.0, 60.0):
+            want = 0
+            for drop in (3, 2, 1):
+                b = k * 2 ** 14 * sum(pairs(s, 3, dx) * 256 ** s for s in range(drop))
+                if math.log2(b) <= budget and b < q / 2:
+                    want = drop
+                    break
+            p = hlb.plan_trunc_b(k, q, q, 1 << 20, budget, "int8")
+            assert p["dropped_shifts"] == want and p["truncated"] == (want > 0)
+            assert p["products"] == 3 * dx - sum(pairs(s, 3, dx) for s in range(want))
+    # no truncation when the K range needs a fold
+    assert hlb.plan_trunc_b(50000, Q50, Q50, 1 << 20, 60.0, "int8")["truncated"] == 0
+    # FP64: (k + 2) 2^-52 k pmax (q/2)
+    k, q, pm = 8192, Q50, 1 << 20
+    p = hlb.plan_trunc_b(k, q, q, pm, 45.0, "fp64")
+    assert p["truncated"] and p["products"] == 1
+    assert abs(p["err_bound_log2"] - math.log2((k + 2) * 2.0 ** -52 * k * pm * (q // 2))) < 1e-9
+    assert not hlb.plan_trunc_b(k, q, q, pm, 42.0, "fp64")["truncated"]
+    assert not hlb.plan_trunc_b(1 << 20, q, q, 1 << 32, 200.0, "fp64")["truncated"]  # k pmax > 2^51
+    with pytest.raises(hlb.HlbError):
+        hlb.plan_trunc_b(10, Q50, 7, 1, 40.0, "int8")   # q_min > q_max
