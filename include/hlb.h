@@ -219,8 +219,12 @@ typedef enum {
                                  the kernel's K step); 0 restores the planned chunk */
     HLB_OPT_PROFILE = 2,      /* 1: bracket every kernel launch with HIP events */
     HLB_OPT_BATCH_GRAPH = 3,  /* 1 (default): capture/replay batches as HIP graphs; 0: eager */
-    HLB_OPT_FORCE_CLASS = 4   /* INT8 tile class: -1 (default) = tuned/heuristic choice,
+    HLB_OPT_FORCE_CLASS = 4,  /* INT8 tile class: -1 (default) = tuned/heuristic choice,
                                  0 = 128 x 64 output tiles, 1 = 64 x 128 output tiles */
+    HLB_OPT_F64_PLANES = 5    /* FP64 form with one plaintext limb: 1 (default) = convert the
+                                 operands into double planes (library workspace), then the
+                                 direct-to-LDS GEMM; 0 = the register-staged kernel, which
+                                 needs no workspace.  Results are identical. */
 } hlb_option;
 
 hlb_status hlb_set_option(int option, int64_t value);

@@ -28,6 +28,7 @@ static std::atomic<int64_t> g_force_kchunk{0};
 static std::atomic<int> g_profile{0};
 static std::atomic<int> g_batch_graph{1};
 static std::atomic<int> g_force_class{-1};
+static std::atomic<int> g_f64_planes{1};
 
 int64_t opt_force_kchunk() { return g_force_kchunk.load(); }
 bool opt_batch_graph() { return g_batch_graph.load() != 0; }
@@ -381,12 +382,19 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
         return HLB_EINVAL;
 
     void *wsP = nullptr, *wsX = nullptr;
-    const int64_t p_tile = (int64_t)pl.np * pl.bm * kBK8, x_tile = (int64_t)pl.nx * pl.bn * kBK8;
+    // FP64 plans with one plaintext limb run on prepared double planes (unless switched off)
+    const bool planes = pl.form == HLB_FORM_FP64 && pl.np == 1 && g_f64_planes.load() != 0 &&
+                        (pl.trunc ? pl.nx == 1 : (pl.nx == 3 || pl.nx == 4));
+    int64_t p_tile = (int64_t)pl.np * pl.bm * kBK8, x_tile = (int64_t)pl.nx * pl.bn * kBK8;
+    if (planes) {
+        p_tile = f64_plane_bytes_p(1, 1);
+        x_tile = f64_plane_bytes_x(pl.nx, 1, 1);
+    }
     auto release = [&]() {
         ws_free(wsP, s);
         ws_free(wsX, s);
     };
-    if (pl.form == HLB_FORM_INT8) {
+    if (pl.form == HLB_FORM_INT8 || planes) {
         hlb_status st = ws_alloc(&wsP, (size_t)(tiles_mmax * kblocks * p_tile), s);
         if (st != HLB_OK) return st;
         st = ws_alloc(&wsX, (size_t)(tiles_total * kblocks * x_tile), s);
@@ -396,10 +404,15 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
         }
         int64_t t0 = 0;
         for (size_t i = 0; i < rights.size(); ++i) {
-            ProfScope ps("split_x", s);
+            ProfScope ps(planes ? "prep_x" : "split_x", s);
             int8_t *dst = (int8_t *)wsX + t0 * kblocks * x_tile;
-            if (launch_split_cols_i8(pl.nx, pl.bn, rights[i].X, rights[i].ldx, k, rights[i].n, (int)seg_tiles[i],
-                                     (int)kblocks, dst, s) != hipSuccess) {
+            const hipError_t e =
+                planes ? launch_prep_x_planes(pl.nx, pl.trunc, rights[i].X, rights[i].ldx, k, rights[i].n,
+                                              (int)seg_tiles[i], (int)kblocks, pl.limb_bits, rights[i].q,
+                                              (double *)dst, s)
+                       : launch_split_cols_i8(pl.nx, pl.bn, rights[i].X, rights[i].ldx, k, rights[i].n,
+                                              (int)seg_tiles[i], (int)kblocks, dst, s);
+            if (e != hipSuccess) {
                 release();
                 return HLB_EDEVICE;
             }
@@ -410,11 +423,14 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
     for (const LeftSpec &L : lefts) {
         if (L.m == 0) continue;
         const int64_t tiles_m = (L.m + pl.bm - 1) / pl.bm;
-        if (pl.form == HLB_FORM_INT8) {
+        if (pl.form == HLB_FORM_INT8 || planes) {
             // stream order: this split runs after the previous left operand's GEMM has read wsP
-            ProfScope ps("split_p", s);
-            if (launch_split_rows_i8(pl.np, pl.bm, L.P, L.ldp, L.m, k, (int)tiles_m, (int)kblocks, (int8_t *)wsP,
-                                     s) != hipSuccess) {
+            ProfScope ps(planes ? "prep_p" : "split_p", s);
+            const hipError_t e =
+                planes ? launch_prep_p_planes(L.P, L.ldp, L.m, k, (int)tiles_m, (int)kblocks, (double *)wsP, s)
+                       : launch_split_rows_i8(pl.np, pl.bm, L.P, L.ldp, L.m, k, (int)tiles_m, (int)kblocks,
+                                              (int8_t *)wsP, s);
+            if (e != hipSuccess) {
                 release();
                 return HLB_EDEVICE;
             }
@@ -459,6 +475,9 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
             } else if (pl.form == HLB_FORM_INT8) {
                 ProfScope ps("gemm_i8", s);
                 e = launch_gemm_i8(pl.np, pl.nx, pl.cls, a, s);
+            } else if (planes) {
+                ProfScope ps(pl.trunc ? "gemm_f64_trunc" : "gemm_f64", s);
+                e = launch_gemm_f64_planes(pl.nx, pl.trunc, a, s);
             } else if (pl.trunc) {
                 ProfScope ps("gemm_f64_trunc", s);
                 e = launch_gemm_f64_trunc(a, s);
@@ -788,6 +807,9 @@ hlb_status hlb_set_option(int option, int64_t value) {
         case HLB_OPT_FORCE_CLASS:
             if (value < -1 || value > 1) return HLB_EINVAL;
             g_force_class.store((int)value);
+            return HLB_OK;
+        case HLB_OPT_F64_PLANES:
+            g_f64_planes.store(value ? 1 : 0);
             return HLB_OK;
         default: return HLB_EUNSUP;
     }

@@ -10,7 +10,9 @@
 // shift s = i + j share one FP64 accumulator; the host sizes w and the K chunk so that
 // pairs * kchunk * max|P_i| * max|X_j| < 2^53, folding longer K into 64-bit residues.
 //
-// No workspace: the limb split happens on the way from global memory into LDS.
+// This kernel needs no workspace: the limb split happens on the way from global memory into
+// LDS (register-staged).  It serves every limb count; the one-plaintext-limb plans of the
+// CP-MM run by default on the plane kernel of gemm_f64_planes.hip instead.
 //
 // TRUNC = true is Strategy 2 of Section 6.1 instead: one FP64 product of the operands
 // rounded to doubles (the plaintext as a signed integer, the residues in their centred

@@ -60,65 +60,6 @@ __device__ __forceinline__ uint64_t recombine_i8(const int (&c)[NS], uint64_t q,
     return r;
 }
 
-// Copies CHUNKS 16-byte chunks from global memory to LDS with the gfx950 direct-to-LDS
-// load: lane l of a wave writes its 16 bytes at (wave-uniform LDS base) + 16 l, so the
-// linear chunk order of the tile-major workspace arrives unchanged and no staging
-// registers are used.  Chunks are dealt to waves in runs of 64.
-template <int THREADS, int CHUNKS>
-__device__ __forceinline__ void copy_to_lds(const int8_t *src, int8_t *dst, int tid, int wave_u) {
-#pragma unroll
-    for (int i = 0; i < (CHUNKS + THREADS - 1) / THREADS; ++i) {
-        const int base = i * THREADS + wave_u * 64;  // wave-uniform
-        if (CHUNKS % THREADS == 0 || base < CHUNKS)
-            __builtin_amdgcn_global_load_lds(
-                (const __attribute__((address_space(1))) void *)(src + (i * THREADS + tid) * 16),
-                (__attribute__((address_space(3))) void *)(dst + base * 16), 16, 0, 0);
-    }
-}
-
-// s_waitcnt vmcnt(n) for a wave-uniform n known only at run time (the immediate must be a
-// constant, so the possible counts are enumerated).
-__device__ __forceinline__ void wait_vmcnt(int n) {
-    switch (n) {
-        case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
-        case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
-        case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
-        case 3: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
-        case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
-        case 5: asm volatile("s_waitcnt vmcnt(5)" ::: "memory"); break;
-        case 6: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
-        case 7: asm volatile("s_waitcnt vmcnt(7)" ::: "memory"); break;
-        case 8: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
-        case 9: asm volatile("s_waitcnt vmcnt(9)" ::: "memory"); break;
-        case 10: asm volatile("s_waitcnt vmcnt(10)" ::: "memory"); break;
-        case 11: asm volatile("s_waitcnt vmcnt(11)" ::: "memory"); break;
-        case 12: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
-        case 13: asm volatile("s_waitcnt vmcnt(13)" ::: "memory"); break;
-        case 14: asm volatile("s_waitcnt vmcnt(14)" ::: "memory"); break;
-        default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
-    }
-}
-
-// Direct-to-LDS loads a wave issues for one stage (chunks are dealt in runs of 64).
-template <int THREADS, int CHUNKS>
-__device__ __forceinline__ int loads_of_wave(int wave_u) {
-    int n = 0;
-#pragma unroll
-    for (int i = 0; i < (CHUNKS + THREADS - 1) / THREADS; ++i) n += (i * THREADS + wave_u * 64 < CHUNKS);
-    return n;
-}
-
-// Workgroup barrier WITHOUT the memory fence of __syncthreads(): that fence waits for every
-// outstanding global load (vmcnt(0)), which would also wait for the direct-to-LDS loads of
-// the stages still in flight.  Visibility is handled explicitly instead: each wave waits
-// (wait_vmcnt) for the loads of the stage about to be read, and its own LDS reads of the
-// stage about to be overwritten have completed because the MFMAs consumed them.
-__device__ __forceinline__ void stage_barrier() {
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
-
 // Scheduling hint for the code just before it: alternate one MFMA with one LDS read, N times,
 // so the fragment reads of the next K half spread over the MFMAs of the current one instead
 // of bunching at the start (mask 0x008 = MFMA, 0x100 = DS read).

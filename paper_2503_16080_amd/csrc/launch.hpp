@@ -34,9 +34,19 @@ hipError_t launch_gemm_i8_batch(int dp, int dx, bool fold, const BatchArgs &a, i
 
 // FP64 form: limb counts of each operand; returns false when no instantiation exists.
 bool f64_supported(int np, int nx);
+// Register-staged kernel (any limb counts f64_supported accepts; no workspace).
 hipError_t launch_gemm_f64(int np, int nx, const GemmArgs &a, hipStream_t s);
 // One FP64 product of the rounded operands (plaintext signed, residues centred), reduced mod q.
 hipError_t launch_gemm_f64_trunc(const GemmArgs &a, hipStream_t s);
+// Plane path for one plaintext limb: preparation into double planes, then the direct-to-LDS
+// GEMM (nx = 3 or 4 limbs; or nx = 1 with trunc, Strategy 2).  Workspace bytes per operand:
+int64_t f64_plane_bytes_p(int64_t tiles_m, int64_t kblocks);
+int64_t f64_plane_bytes_x(int nx, int64_t tiles_n, int64_t kblocks);
+hipError_t launch_prep_p_planes(const int64_t *P, int64_t ldp, int64_t m, int64_t k, int tiles, int kblocks,
+                                double *out, hipStream_t s);
+hipError_t launch_prep_x_planes(int nx, bool trunc, const uint64_t *X, int64_t ldx, int64_t k, int64_t n, int tiles,
+                                int kblocks, int w, uint64_t q, double *out, hipStream_t s);
+hipError_t launch_gemm_f64_planes(int nx, bool trunc, const GemmArgs &a, hipStream_t s);
 
 // Auxiliary kernels.
 hipError_t launch_validate(const uint64_t *X, int64_t rows, int64_t cols, int64_t ld, uint64_t q,

@@ -71,7 +71,7 @@ def test_budget_below_every_truncation_gives_the_exact_cp_mm():
         assert np.array_equal(_np(PA), wantA) and np.array_equal(_np(PB), wantB)
 
 
-@pytest.mark.parametrize("shape", [(64, 64, 64), (100, 513, 77), (33, 1000, 129)])
+@pytest.mark.parametrize("shape", [(64, 64, 64), (100, 513, 77), (33, 1000, 129), (100, 514, 78)])
 def test_fp64_trunc_within_bound(shape):
     m, k, n = shape
     w = wl.cpmm_uniform(3200 + k, m, k, n, 50, 1)
