@@ -40,6 +40,7 @@ def _parse():
     ap.add_argument("--bits", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-limb and dgemm legs")
+    ap.add_argument("--no-crt", action="store_true", help="skip the multimodular INT8 leg")
     ap.add_argument("--workload", choices=["cpmm", "batch", "trunc"], default="cpmm",
                     help="cpmm: one CP-MM of size --d (default); batch: 64 CP-MMs of uneven "
                          "shapes over 4 primes of 45 bits; trunc: the CP-MM of size --d with "
@@ -335,6 +336,37 @@ def main():
         "kernels_ms": {"gemm_i8": gemm_ms, "split_p": ms_sp / max(n_sp, 1),
                        "split_x_per_matrix": ms_sx / max(n_sx, 1)},
     }
+
+    if not args.no_crt:
+        # multimodular INT8 form (Strategy 3): D int8 products instead of the digit pairs
+        for _ in range(args.warmup):
+            step("int8_crt")()
+        torch.cuda.synchronize()
+        hlb.profile_reset()
+        hlb.set_option(hlb.OPT_PROFILE, 1)
+        s_crt = _time_steps(step("int8_crt"), args.steps, 0)
+        hlb.set_option(hlb.OPT_PROFILE, 0)
+        prof = {name: hlb.profile_read(name) for name in ("crt_gemm", "crt_split_p", "crt_split_x", "crt_combine")}
+        hlb.profile_reset()
+        cplan = hlb.plan(1, d, max(w.primes), w.p_absmax, "int8_crt")
+        # the narrower GEMM tile, for comparison
+        hlb.set_option(hlb.OPT_CRT_WIDE, 0)
+        step("int8_crt")()
+        torch.cuda.synchronize()
+        hlb.set_option(hlb.OPT_PROFILE, 1)
+        _time_steps(step("int8_crt"), max(2, args.steps // 3), 0)
+        hlb.set_option(hlb.OPT_PROFILE, 0)
+        hlb.set_option(hlb.OPT_CRT_WIDE, 1)
+        n_narrow, t_narrow = hlb.profile_read("crt_gemm")
+        hlb.profile_reset()
+        c_ms = prof["crt_gemm"][1] / max(prof["crt_gemm"][0], 1)
+        c_ops = 2.0 * cplan["p_limbs"] * macs
+        out["int8_crt_form"] = {
+            "value": macs / s_crt, "unit": "mod-q MAC/s", "ms_per_step": s_crt * 1e3, "moduli": cplan["p_limbs"],
+            "gemm_ms": c_ms, "gemm_tops": c_ops / (c_ms * 1e-3) / 1e12,
+            "gemm_frac_of_int8_peak": c_ops / (c_ms * 1e-3) / 1e12 / INT8_PEAK_TOPS,
+            "kernels_ms": {n: t / max(c, 1) for n, (c, t) in prof.items()},
+            "gemm_ms_256x128_tile": t_narrow / max(n_narrow, 1)}
 
     if not args.no_fp64:
         fp_steps = max(2, args.steps // 3)

@@ -51,9 +51,12 @@ typedef enum {
 } hlb_status;
 
 typedef enum {
-    HLB_FORM_AUTO = 0, /* INT8 where a plan exists, else FP64 */
-    HLB_FORM_FP64 = 1, /* FP64 limbs on v_mfma_f64_16x16x4_f64 */
-    HLB_FORM_INT8 = 2  /* balanced int8 digits on v_mfma_i32_32x32x32_i8 */
+    HLB_FORM_AUTO = 0,     /* INT8 where a plan exists, else FP64 */
+    HLB_FORM_FP64 = 1,     /* FP64 limbs on v_mfma_f64_16x16x4_f64 */
+    HLB_FORM_INT8 = 2,     /* balanced int8 digits on v_mfma_i32_32x32x32_i8 (Strategy 1) */
+    HLB_FORM_INT8_CRT = 3  /* multimodular: the centred integer product modulo D coprime
+                              moduli <= 256, one int8 GEMM each, recombined by the CRT
+                              (Strategy 3, FLINT variant); needs k <= 131071 */
 } hlb_form;
 
 /* Human-readable name of a status code (static string, never NULL). */
@@ -221,10 +224,12 @@ typedef enum {
     HLB_OPT_BATCH_GRAPH = 3,  /* 1 (default): capture/replay batches as HIP graphs; 0: eager */
     HLB_OPT_FORCE_CLASS = 4,  /* INT8 tile class: -1 (default) = tuned/heuristic choice,
                                  0 = 128 x 64 output tiles, 1 = 64 x 128 output tiles */
-    HLB_OPT_F64_PLANES = 5    /* FP64 form with one plaintext limb: 1 (default) = convert the
+    HLB_OPT_F64_PLANES = 5,   /* FP64 form with one plaintext limb: 1 (default) = convert the
                                  operands into double planes (library workspace), then the
                                  direct-to-LDS GEMM; 0 = the register-staged kernel, which
                                  needs no workspace.  Results are identical. */
+    HLB_OPT_CRT_WIDE = 6      /* multimodular GEMM tile: 1 (default) = 256 x 256 outputs,
+                                 0 = 256 x 128.  Results are identical. */
 } hlb_option;
 
 hlb_status hlb_set_option(int option, int64_t value);

@@ -18,6 +18,7 @@
 #include "common.hpp"
 #include "launch.hpp"
 #include "host.hpp"
+#include "crt.hpp"
 
 namespace hlb {
 
@@ -29,6 +30,7 @@ static std::atomic<int> g_profile{0};
 static std::atomic<int> g_batch_graph{1};
 static std::atomic<int> g_force_class{-1};
 static std::atomic<int> g_f64_planes{1};
+static std::atomic<int> g_crt_wide{1};
 
 int64_t opt_force_kchunk() { return g_force_kchunk.load(); }
 bool opt_batch_graph() { return g_batch_graph.load() != 0; }
@@ -220,6 +222,7 @@ hlb_status plan_trunc_b(int64_t k, uint64_t qmin, uint64_t qmax, int64_t pmax, d
     if (st != HLB_OK) return st;
     const double half_qmin = std::log2((double)qmin) - 1.0;
     const double kk = (double)std::max<int64_t>(k, 1);
+    if (pl->form == HLB_FORM_INT8_CRT) return HLB_OK;  // no truncated variant: the exact plan
     if (pl->form == HLB_FORM_INT8) {
         if (pl->np != 3 || k > pl->kchunk) return HLB_OK;
         for (int drop = 3; drop >= 1; --drop) {
@@ -256,9 +259,38 @@ hlb_status plan_trunc_b(int64_t k, uint64_t qmin, uint64_t qmax, int64_t pmax, d
     return HLB_OK;
 }
 
+// Multimodular plan (Strategy 3): the centred product satisfies |V| <= k * a * b with
+// a = p_absmax (plaintext) or floor(q/2) (residues) and b = floor(q/2); the first D moduli
+// must multiply to at least 4 |V| (so that |V| / M <= 1/4), and |c| <= k 2^14 < 2^31.
+hlb_status plan_crt(int kind, int64_t k, uint64_t qmax, int64_t pmax, Plan *pl) {
+    if (k > 131071) return HLB_EBOUND;
+    const double half_q = (double)(qmax / 2 > 0 ? qmax / 2 : 1);
+    const double a = kind == 1 ? (double)std::max<int64_t>(pmax, 1) : half_q;
+    const double need = std::log2((double)std::max<int64_t>(k, 1)) + std::log2(a) + std::log2(half_q) + 2.0;
+    double have = 0.0;
+    int D = 0;
+    while (D < kCrtMaxModuli && have < need) have += std::log2((double)kCrtModuli[D++]);
+    if (have < need) return HLB_EBOUND;
+    D = crt_round_d(D);
+    if (D == 0) return HLB_EBOUND;
+    pl->form = HLB_FORM_INT8_CRT;
+    pl->np = D;
+    pl->nx = D;
+    pl->limb_bits = 8;
+    pl->pairs = 1;
+    pl->kchunk = std::max<int64_t>(k, kBK8);
+    pl->bm = 256;
+    pl->bn = 128;
+    pl->bk = kBK8;
+    pl->acc_bound_log2 = std::log2((double)std::max<int64_t>(k, 1) * 16384.0);
+    return HLB_OK;
+}
+
 hlb_status plan(int kind, int64_t k, uint64_t qmax, int64_t pmax, int form, Plan *pl) {
+    pl->kind = kind;
     if (form == HLB_FORM_INT8) return plan_i8(kind, k, qmax, pmax, pl);
     if (form == HLB_FORM_FP64) return plan_f64(kind, k, qmax, pmax, pl);
+    if (form == HLB_FORM_INT8_CRT) return plan_crt(kind, k, qmax, pmax, pl);
     if (form == HLB_FORM_AUTO) {
         if (plan_i8(kind, k, qmax, pmax, pl) == HLB_OK) return HLB_OK;
         return plan_f64(kind, k, qmax, pmax, pl);
@@ -350,6 +382,148 @@ void ws_free(void *p, hipStream_t s) {
 // ---------------------------------------------------------------------------------------
 // One GEMM launch over up to kMaxSegs output segments sharing the left operand.
 // ---------------------------------------------------------------------------------------
+// Multimodular form of run_products: residue splits of every right operand and of each left
+// operand, one INT8 GEMM launch per left operand and group of up to kMaxSegs right operands
+// (all D moduli in one grid), then one recombination launch per output matrix.
+static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &lefts,
+                                   const std::vector<RightSpec> &rights, int64_t k, int n_xcd, hipStream_t s) {
+    const int D = pl.np;
+    const int wide = g_crt_wide.load();
+    const int64_t bn = crt_tile_cols(wide), xsub = bn / 128;
+    const int64_t kblocks = (k + kBK8 - 1) / kBK8;
+    const int64_t sub = (int64_t)D * 128 * kBK8;  // bytes of one 128-wide tile and k block
+    int64_t mmax = 0;
+    for (const LeftSpec &L : lefts) mmax = std::max(mmax, L.m);
+    const int64_t t128_m = ((mmax + 255) / 256) * 2;  // 128-row tiles, even: GEMM tiles are 256 rows
+    // per right operand: GEMM column tiles, and the 128-column split tiles that back them
+    std::vector<int64_t> tg_n(rights.size()), t128_n(rights.size());
+    int64_t tn_total = 0, ybytes = 0;
+    for (size_t i = 0; i < rights.size(); ++i) {
+        tg_n[i] = (rights[i].n + bn - 1) / bn;
+        t128_n[i] = tg_n[i] * xsub;
+        tn_total += t128_n[i];
+        ybytes += (int64_t)D * mmax * ((rights[i].n + 15) / 16 * 16);
+    }
+    if (kblocks > INT32_MAX / 2 || t128_m * kblocks > INT32_MAX / 2 || tn_total * kblocks > INT32_MAX / 2 ||
+        (int64_t)D * (t128_m / 2) * tn_total > INT32_MAX / 2)
+        return HLB_EINVAL;
+
+    // constants: M = prod p_i, inv_i = (M / p_i)^{-1} mod p_i
+    unsigned __int128 M = 1;
+    for (int i = 0; i < D; ++i) M *= (unsigned)kCrtModuli[i];
+    int32_t inv[kCrtMaxModuli] = {0};
+    for (int i = 0; i < D; ++i) {
+        const int p = kCrtModuli[i];
+        const int mi = (int)((M / (unsigned)p) % (unsigned)p);
+        for (int v = 1; v < p; ++v)
+            if ((mi * v) % p == 1) {
+                inv[i] = v;
+                break;
+            }
+    }
+
+    void *wsP = nullptr, *wsX = nullptr, *wsY = nullptr;
+    auto release = [&]() {
+        ws_free(wsP, s);
+        ws_free(wsX, s);
+        ws_free(wsY, s);
+    };
+    hlb_status st = ws_alloc(&wsP, (size_t)(t128_m * kblocks * sub), s);
+    if (st == HLB_OK) st = ws_alloc(&wsX, (size_t)(tn_total * kblocks * sub), s);
+    if (st == HLB_OK) st = ws_alloc(&wsY, (size_t)ybytes, s);
+    if (st != HLB_OK) {
+        release();
+        return st;
+    }
+    int64_t t0 = 0;
+    for (size_t i = 0; i < rights.size(); ++i) {
+        ProfScope ps("crt_split_x", s);
+        if (launch_crt_split_cols(D, rights[i].X, rights[i].ldx, k, rights[i].n, (int)t128_n[i], (int)kblocks,
+                                  rights[i].q, (int8_t *)wsX + t0 * kblocks * sub, s) != hipSuccess) {
+            release();
+            return HLB_EDEVICE;
+        }
+        t0 += t128_n[i];
+    }
+    // a left operand holding residues is centred modulo the (shared) modulus of the products
+    const uint64_t left_qc = pl.kind == 0 ? rights[0].q : 0;
+    for (const LeftSpec &L : lefts) {
+        if (L.m == 0) continue;
+        const int64_t lt = ((L.m + 255) / 256) * 2;
+        {
+            ProfScope ps("crt_split_p", s);
+            if (launch_crt_split_rows(D, L.P, L.ldp, L.m, k, (int)lt, (int)kblocks, left_qc, (int8_t *)wsP, s) !=
+                hipSuccess) {
+                release();
+                return HLB_EDEVICE;
+            }
+        }
+        int64_t tile_base = 0;
+        for (size_t first = 0; first < rights.size(); first += kMaxSegs) {
+            const size_t last = std::min(rights.size(), first + kMaxSegs);
+            CrtGemmArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.Pd = (const int8_t *)wsP;
+            a.Xd = (const int8_t *)wsX + tile_base * xsub * kblocks * sub;
+            a.m = L.m;
+            a.kblocks = (int)kblocks;
+            a.D = D;
+            a.tiles_m = (int)(lt / 2);
+            a.group_m = 4;
+            a.n_xcd = n_xcd;
+            for (int i = 0; i < D; ++i) a.inv[i] = inv[i];
+            int32_t tb = 0;
+            int64_t yoff = 0;
+            for (size_t i = first; i < last; ++i) {
+                CrtSeg &sg = a.seg[a.nseg++];
+                sg.Y = (uint8_t *)wsY + yoff;
+                sg.n = rights[i].n;
+                sg.ldy = (rights[i].n + 15) / 16 * 16;
+                sg.tile_begin = tb;
+                tb += (int32_t)tg_n[i];
+                yoff += (int64_t)D * L.m * sg.ldy;
+            }
+            a.tiles_n = tb;
+            tile_base += tb;
+            if (tb == 0) continue;
+            {
+                ProfScope ps("crt_gemm", s);
+                if (launch_crt_gemm(wide, a, s) != hipSuccess) {
+                    release();
+                    return HLB_EDEVICE;
+                }
+            }
+            for (size_t i = first; i < last; ++i) {
+                const CrtSeg &sg = a.seg[i - first];
+                if (sg.n == 0) continue;
+                CrtCombineArgs c;
+                std::memset(&c, 0, sizeof(c));
+                c.Y = sg.Y;
+                c.C = L.C[i];
+                c.m = L.m;
+                c.n = sg.n;
+                c.ldy = sg.ldy;
+                c.ldc = L.ldc[i];
+                c.q = rights[i].q;
+                c.barrett = (uint64_t)((~(unsigned __int128)0 >> 64) / c.q);
+                c.Mq = (uint64_t)(M % c.q);
+                c.D = D;
+                for (int j = 0; j < D; ++j) {
+                    c.w[j] = (uint64_t)((M / (unsigned)kCrtModuli[j]) % c.q);
+                    c.pinv[j] = 1.0f / (float)kCrtModuli[j];
+                }
+                ProfScope ps("crt_combine", s);
+                if (launch_crt_combine(c, s) != hipSuccess) {
+                    release();
+                    return HLB_EDEVICE;
+                }
+            }
+        }
+    }
+    release();
+    return HLB_OK;
+}
+
 // Runs C[l][r] = L_l * X_r mod q_r for every left operand L_l and right operand X_r.  Each
 // right operand is split once and shared by all left operands; each left operand is split
 // once and shared by all right operands; then one GEMM launch per left operand covers up to
@@ -368,6 +542,7 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
                     return HLB_EDEVICE;
         return HLB_OK;
     }
+    if (pl.form == HLB_FORM_INT8_CRT) return run_products_crt(pl, lefts, rights, k, n_xcd, s);
     const int64_t tiles_mmax = (mmax + pl.bm - 1) / pl.bm;
     const int64_t kblocks = (k + pl.bk - 1) / pl.bk;
     const int64_t kfold = std::max<int64_t>(1, pl.kchunk / pl.bk);
@@ -810,6 +985,9 @@ hlb_status hlb_set_option(int option, int64_t value) {
             return HLB_OK;
         case HLB_OPT_F64_PLANES:
             g_f64_planes.store(value ? 1 : 0);
+            return HLB_OK;
+        case HLB_OPT_CRT_WIDE:
+            g_crt_wide.store(value ? 1 : 0);
             return HLB_OK;
         default: return HLB_EUNSUP;
     }

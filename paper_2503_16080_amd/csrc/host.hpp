@@ -16,7 +16,8 @@ namespace hlb {
 // accumulator inside the exact range of its type (Lemma le:strategy1).
 struct Plan {
     int form = 0;
-    int np = 0, nx = 0;     // limbs of the left / right operand (instantiated counts)
+    int kind = 1;           // 0: both operands residues (Mod-PP-MM); 1: signed plaintext on the left
+    int np = 0, nx = 0;     // limbs of the left / right operand (instantiated counts); CRT: moduli
     int limb_bits = 0;
     int pairs = 0;          // most limb products sharing one accumulator
     int64_t kchunk = 0;     // K elements accumulated before a fold

@@ -48,6 +48,21 @@ hipError_t launch_prep_x_planes(int nx, bool trunc, const uint64_t *X, int64_t l
                                 int kblocks, int w, uint64_t q, double *out, hipStream_t s);
 hipError_t launch_gemm_f64_planes(int nx, bool trunc, const GemmArgs &a, hipStream_t s);
 
+// Multimodular (CRT) INT8 form: residue splits (qc = 0: signed values; else residues mod qc
+// taken centred), one INT8 GEMM per modulus, recombination.  D must be crt_supported_d.
+bool crt_supported_d(int D);
+int crt_round_d(int D);  // smallest supported D >= D, or 0
+hipError_t launch_crt_split_rows(int D, const int64_t *P, int64_t ldp, int64_t m, int64_t k, int tiles, int kblocks,
+                                 uint64_t qc, int8_t *out, hipStream_t s);
+hipError_t launch_crt_split_cols(int D, const uint64_t *X, int64_t ldx, int64_t k, int64_t n, int tiles, int kblocks,
+                                 uint64_t qc, int8_t *out, hipStream_t s);
+struct CrtGemmArgs;
+struct CrtCombineArgs;
+// wide = 0: 256 x 128 output tiles; 1: 256 x 256.  crt_tile_cols gives the tile width.
+int crt_tile_cols(int wide);
+hipError_t launch_crt_gemm(int wide, const CrtGemmArgs &a, hipStream_t s);
+hipError_t launch_crt_combine(const CrtCombineArgs &a, hipStream_t s);
+
 // Auxiliary kernels.
 hipError_t launch_validate(const uint64_t *X, int64_t rows, int64_t cols, int64_t ld, uint64_t q,
                            unsigned long long *first_bad, hipStream_t s);

@@ -208,3 +208,27 @@ def test_trunc_b_planner_bounds():
     assert not hlb.plan_trunc_b(1 << 20, q, q, 1 << 32, 200.0, "fp64")["truncated"]  # k pmax > 2^51
     with pytest.raises(hlb.HlbError):
         hlb.plan_trunc_b(10, Q50, 7, 1, 40.0, "int8")   # q_min > q_max
+
+
+def test_crt_plan_moduli_count():
+    # the smallest number of the fixed coprime moduli whose product is at least 4 |V|,
+    # |V| <= k * a * floor(q/2), rounded up to an instantiated count
+    import math
+    mods = [256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211, 199, 197, 193, 191]
+    for a_ in range(len(mods)):
+        for b_ in range(a_ + 1, len(mods)):
+            assert math.gcd(mods[a_], mods[b_]) == 1
+    inst = [8, 10, 11, 12, 14, 16]
+    for kind, k, q, pm in ((1, 8192, Q50, 1 << 20), (1, 256, Q50, 1 << 20), (0, 8192, Q50, 1),
+                           (1, 4096, wl.ntt_primes(45, 1)[0], 1 << 20), (0, 100, 97, 1)):
+        a = pm if kind == 1 else q // 2
+        need = math.log2(k) + math.log2(a) + math.log2(max(q // 2, 1)) + 2
+        D, have = 0, 0.0
+        while have < need:
+            have += math.log2(mods[D])
+            D += 1
+        D = min(d for d in inst if d >= D)
+        p = hlb.plan(kind, k, q, pm, "int8_crt")
+        assert p["form"] == 3 and p["p_limbs"] == D
+    with pytest.raises(hlb.HlbError):
+        hlb.plan(1, 131072, Q50, 1 << 20, "int8_crt")

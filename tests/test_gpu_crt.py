@@ -1,0 +1,131 @@
+"""GPU parity of the multimodular (CRT) INT8 form against the oracle, bit for bit.
+
+The form computes the exact integer product modulo small coprime moduli and recombines it,
+so its result is the unique canonical residue, like every other form: the oracle is the plain
+definition of Mod-PP-MM / CP-MM."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2503_16080_amd as hlb
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _t(a):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    return torch.from_numpy(a).to(DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("wide", [1, 0])
+@pytest.mark.parametrize("dims", [(1, 1, 1, 1, 1), (33, 65, 17, 40, 1), (256, 128, 128, 128, 2),
+                                  (200, 300, 130, 70, 3), (300, 64, 257, 1, 4), (64, 700, 64, 0, 2),
+                                  (513, 129, 255, 129, 1), (100, 200, 600, 300, 1)])
+def test_cp_mm_crt_vs_oracle(dims, wide):
+    m, k, nA, nB, L = dims
+    w = wl.cpmm_uniform(5000 + sum(dims), m, k, max(nA, nB, 1), 50, L)
+    A, B = w.A[:, :, :nA], w.B[:, :, :nB]
+    try:
+        hlb.set_option(hlb.OPT_CRT_WIDE, wide)
+        PA, PB = hlb.cp_mm(_t(w.P), _t(A), _t(B), w.primes, p_absmax=w.p_absmax, form="int8_crt")
+        got = (_np(PA), _np(PB))
+    finally:
+        hlb.set_option(hlb.OPT_CRT_WIDE, 1)
+    wantA, wantB = oracle.cp_mm(w.P, A, B, w.primes)
+    assert np.array_equal(got[0], wantA) and np.array_equal(got[1], wantB)
+
+
+def test_cp_mm_crt_45_bit_and_measured_bound():
+    w = wl.cpmm_uniform(5100, 190, 333, 150, 45, 4)
+    PA, PB = hlb.cp_mm(_t(w.P), _t(w.A), _t(w.B), w.primes, p_absmax=0, form="int8_crt")
+    wantA, wantB = oracle.cp_mm(w.P, w.A, w.B, w.primes)
+    assert np.array_equal(_np(PA), wantA) and np.array_equal(_np(PB), wantB)
+
+
+@pytest.mark.parametrize("q", [2, 3, 97, 65537, (1 << 31) - 1, (1 << 52) - 47])
+def test_mod_pp_mm_crt_moduli(q):
+    # both operands full residues: the widest moduli sets
+    g = wl.rng(q % 1000)
+    m, k, n = 70, 200, 90
+    P = g.integers(0, q, size=(m, k), dtype=np.uint64)
+    X = g.integers(0, q, size=(k, n), dtype=np.uint64)
+    got = _np(hlb.mod_pp_mm(q, _t(P), _t(X), form="int8_crt"))
+    assert np.array_equal(got, oracle.mod_pp_mm(q, P, X))
+
+
+def test_crt_extreme_values_closed_form():
+    # P = +-p_absmax and A = q - 1 everywhere: (P A)_ij = -sum_l P_il (mod q), exactly
+    primes = wl.ntt_primes(50, 2)
+    m, k, n = 40, 4096, 64
+    for sign in (1, -1):
+        P = np.full((m, k), sign * (1 << 20), dtype=np.int64)
+        A = np.stack([np.full((k, n), q - 1, dtype=np.uint64) for q in primes])
+        PA, PB = hlb.cp_mm(_t(P), _t(A), _t(A), primes, p_absmax=1 << 20, form="int8_crt")
+        PA, PB = _np(PA), _np(PB)
+        for i, q in enumerate(primes):
+            want = (-sign * k * (1 << 20)) % q
+            assert (PA[i] == want).all() and (PB[i] == want).all()
+    # residues q - 1 on both sides (centred -1): every output is k mod q
+    q = (1 << 52) - 47
+    P = np.full((30, 3000), q - 1, dtype=np.uint64)
+    got = _np(hlb.mod_pp_mm(q, _t(P), _t(P.T.copy()), form="int8_crt"))
+    assert (got == 3000 % q).all()
+    # residues (q-1)/2 and (q+1)/2: the two ends of the centred range
+    X = np.full((3000, 20), (q + 1) // 2, dtype=np.uint64)
+    P = np.full((30, 3000), (q - 1) // 2, dtype=np.uint64)
+    got = _np(hlb.mod_pp_mm(q, _t(P), _t(X), form="int8_crt"))
+    assert (got == oracle.mod_pp_mm(q, P[:1], X[:, :1])[0, 0]).all()
+
+
+def test_ccmm_core_crt():
+    primes = wl.ntt_primes(50, 2, skip=1)
+    g = wl.rng(5200)
+    m, k, n = 70, 130, 33
+    A, B = (np.stack([wl.uniform_residues(g, (m, k), q) for q in primes]) for _ in range(2))
+    At, Bt = (np.stack([wl.uniform_residues(g, (k, n), q) for q in primes]) for _ in range(2))
+    got = hlb.ccmm_pp_core(_t(A), _t(B), _t(At), _t(Bt), primes, form="int8_crt")
+    want = oracle.ccmm_pp_core(A, B, At, Bt, primes)
+    for gC, wC in zip(got, want):
+        assert np.array_equal(_np(gC), wC)
+
+
+def test_crt_strided_and_edges():
+    q = wl.ntt_primes(50, 1)[0]
+    g = wl.rng(5300)
+    Pb = g.integers(0, q, size=(50, 90), dtype=np.uint64)
+    Xb = g.integers(0, q, size=(90, 70), dtype=np.uint64)
+    P = _t(Pb)[:, 5:85]          # ldp = 90, k = 80
+    X = _t(Xb)[5:85, 3:60]       # ldx = 70, n = 57
+    got = _np(hlb.mod_pp_mm(q, P, X, form="int8_crt"))
+    assert np.array_equal(got, oracle.mod_pp_mm(q, Pb[:, 5:85], Xb[5:85, 3:60]))
+    # k = 0 writes zeros
+    C = hlb.mod_pp_mm(q, torch.zeros((5, 0), dtype=torch.int64, device=DEV),
+                      torch.zeros((0, 7), dtype=torch.int64, device=DEV), form="int8_crt")
+    assert (_np(C) == 0).all()
+
+
+def test_crt_large_sampled_rows_and_forms_agree():
+    # the d = 4096 shape: sampled rows against the oracle, and the three forms bit-identical
+    d = 4096
+    w = wl.cpmm_uniform(5400, d, d, d, 50, 2)
+    rows = [0, 1, 255, 256, 2047, 4000, 4095]
+    out = {}
+    for form in ("int8_crt", "int8"):
+        PA, PB = hlb.cp_mm(_t(w.P), _t(w.A), _t(w.B), w.primes, p_absmax=w.p_absmax, form=form)
+        out[form] = (_np(PA), _np(PB))
+    assert np.array_equal(out["int8_crt"][0], out["int8"][0])
+    assert np.array_equal(out["int8_crt"][1], out["int8"][1])
+    wantA, wantB = oracle.cp_mm(w.P, w.A, w.B, w.primes, rows=rows)
+    for l in range(2):
+        assert np.array_equal(out["int8_crt"][0][l][rows], wantA[l][rows])
+        assert np.array_equal(out["int8_crt"][1][l][rows], wantB[l][rows])
