@@ -2,14 +2,16 @@
 
 Default workload: CP-MM at d = 8192 -- an 8192 x 8192 plaintext P = floor(2^20 U + 1/2)
 times a ciphertext whose a- and b-parts are 8192 x 8192 residue matrices, over 3 RNS primes
-of 50 bits -- in the INT8-limb form.  One step is one full ``hlb_cp_mm`` call: plaintext
-digit split, ciphertext digit split (all primes and parts), and one limb-GEMM launch with the
-fused recombination / mod-q epilogue, i.e. 2 * L = 6 Mod-PP-MMs of 8192^3.
+of 50 bits -- i.e. 2 * L = 6 Mod-PP-MMs of 8192^3 per step, all bit-exact.
 
-Reported: mod-q MACs/s (2 L m k n per step / step time), the same workload in the FP64-limb
-form, a same-shape vendor FP64 GEMM (torch float64 matmul, d^3) and the resulting slowdown,
-the limb GEMM's roofline position (HIP events around its launches, inside the timed region),
-and the CPU oracle's rate on a bounded row sample.
+The headline is the INT8-limb form in its multimodular variant (Strategy 3): one step is one
+``hlb_cp_mm`` call -- residue splits of the plaintext and of the 6 ciphertext matrices, one
+GEMM launch over all 11 moduli x 6 products, and one recombination per output matrix.
+
+Also reported: the INT8 digit form (Strategy 1, 3 x 7 digit products), the FP64-limb form,
+a same-shape vendor FP64 GEMM (torch float64 matmul, d^3) and the resulting slowdowns, each
+GEMM's roofline position (HIP events around its launches, inside the timed region), and the
+CPU oracle's rate on a bounded row sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -40,7 +42,7 @@ def _parse():
     ap.add_argument("--bits", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-limb and dgemm legs")
-    ap.add_argument("--no-crt", action="store_true", help="skip the multimodular INT8 leg")
+    ap.add_argument("--no-digit", action="store_true", help="skip the digit (Strategy 1) INT8 leg")
     ap.add_argument("--workload", choices=["cpmm", "batch", "trunc"], default="cpmm",
                     help="cpmm: one CP-MM of size --d (default); batch: 64 CP-MMs of uneven "
                          "shapes over 4 primes of 45 bits; trunc: the CP-MM of size --d with "
@@ -56,46 +58,55 @@ def _parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_i8_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2503_16080_amd", "csrc", f) for f in ("gemm_i8.hip", "i8_tile.hpp", "common.hpp")]
+_CSRC = os.path.join(ROOT, "paper_2503_16080_amd", "csrc")
+# Counter summaries per GEMM kernel: the file bench.py reads them from, the sources whose
+# SHA-256 they are valid for, and the kernel-name substring that selects their dispatches.
+TRAFFIC = {
+    "crt_gemm": {"file": os.path.join(ROOT, "profiles", "crt_gemm_traffic.json"),
+                 "sources": [os.path.join(_CSRC, f) for f in ("crt.hip", "crt.hpp", "common.hpp")],
+                 "match": "crt_gemm_kernel"},
+    "gemm_i8": {"file": os.path.join(ROOT, "profiles", "gemm_i8_traffic.json"),
+                "sources": [os.path.join(_CSRC, f) for f in ("gemm_i8.hip", "i8_tile.hpp", "common.hpp")],
+                "match": "gemm_i8_kernel"},
+}
 
 
-def kernel_source_hash() -> str:
-    """SHA-256 over the INT8 limb-GEMM sources: counter data is valid only for this hash."""
+def kernel_source_hash(kernel: str) -> str:
+    """SHA-256 over a GEMM kernel's sources: its counter data is valid only for this hash."""
     import hashlib
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in TRAFFIC[kernel]["sources"]:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(d, L):
-    """HBM bytes per limb-GEMM launch from the committed counter summary, or None when the
+def measured_traffic(kernel, d, L):
+    """HBM bytes per launch of `kernel` from its committed counter summary, or None when the
     summary is missing, is for another workload, or predates the current kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC[kernel]["file"]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256") != kernel_source_hash() or t.get("d") != d or t.get("primes") != L:
+    if t.get("kernel_source_sha256") != kernel_source_hash(kernel) or t.get("d") != d or t.get("primes") != L:
         return None
     return t["fetch_kib"] * 1024 * t["fetch_scale"] + t["write_kib"] * 1024 * t["write_scale"]
 
 
-def summarize_counters(fetch_dir, write_dir, d, L):
+def summarize_counters(fetch_dir, write_dir, d, L, kernel):
     """Turns two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, each with
-    --copy-calibration) into the counter summary: per-dispatch KiB of the limb GEMM and the
-    scale factors that make the 1 GiB calibration copy read and write exactly 1 GiB."""
+    --copy-calibration) into the counter summary of `kernel`: per-dispatch KiB and the scale
+    factors that make the 1 GiB calibration copy read and write exactly 1 GiB."""
     import csv
+    import glob
     import statistics
 
     def per_kernel(path, counter):
-        import glob
         (name,) = glob.glob(os.path.join(path, "*counter_collection.csv"))
         rows = list(csv.DictReader(open(name)))
         gemm = [float(r["Counter_Value"]) for r in rows
-                if r["Counter_Name"] == counter and "gemm_i8_kernel" in r["Kernel_Name"]]
+                if r["Counter_Name"] == counter and TRAFFIC[kernel]["match"] in r["Kernel_Name"]]
         copy = [float(r["Counter_Value"]) for r in rows
                 if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]]
         return statistics.mean(gemm), statistics.mean(copy)
@@ -103,11 +114,11 @@ def summarize_counters(fetch_dir, write_dir, d, L):
     fetch, fcopy = per_kernel(fetch_dir, "FETCH_SIZE")
     write, wcopy = per_kernel(write_dir, "WRITE_SIZE")
     gib_kib = float(1 << 20)
-    out = {"kernel_source_sha256": kernel_source_hash(), "d": d, "primes": L,
+    out = {"kernel": kernel, "kernel_source_sha256": kernel_source_hash(kernel), "d": d, "primes": L,
            "fetch_kib": fetch, "write_kib": write,
            "fetch_scale": gib_kib / fcopy, "write_scale": gib_kib / wcopy,
            "copy_calibration_kib": {"fetch": fcopy, "write": wcopy, "bytes_copied": 1 << 30}}
-    with open(TRAFFIC_FILE, "w") as f:
+    with open(TRAFFIC[kernel]["file"], "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
     return out
@@ -256,7 +267,8 @@ def run_trunc(args):
 def main():
     args = _parse()
     if args.summarize_counters:
-        print(json.dumps(summarize_counters(*args.summarize_counters, args.d, args.primes)))
+        for kernel in TRAFFIC:
+            print(json.dumps(summarize_counters(*args.summarize_counters, args.d, args.primes, kernel)))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the CP-MM path has no multi-GPU leg); "
@@ -297,76 +309,58 @@ def main():
     def step(form):
         return lambda: hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form=form, out=(PA, PB))
 
-    # INT8-limb form: the headline, with the limb GEMM's launches bracketed by HIP events
-    for _ in range(args.warmup):
-        step("int8")()
-    torch.cuda.synchronize()
-    hlb.profile_reset()
-    hlb.set_option(hlb.OPT_PROFILE, 1)
-    s_int8 = _time_steps(step("int8"), args.steps, 0)
-    hlb.set_option(hlb.OPT_PROFILE, 0)
-    n_gemm, ms_gemm = hlb.profile_read("gemm_i8")
-    n_sp, ms_sp = hlb.profile_read("split_p")
-    n_sx, ms_sx = hlb.profile_read("split_x")
-    hlb.profile_reset()
-    gemm_ms = ms_gemm / max(n_gemm, 1)
-    plan = hlb.plan(1, d, max(w.primes), w.p_absmax, "int8")
-    limb_products = plan["p_limbs"] * plan["x_limbs"]
-    # algorithmic int8 ops of one launch: 2 per MAC, limb_products MACs per mod-q MAC
-    ops = 2.0 * limb_products * macs
-    achieved_tops = ops / (gemm_ms * 1e-3) / 1e12
+    def timed(form, names, steps, warmup):
+        """Step time of `form` with its kernels bracketed by HIP events on the launch stream."""
+        for _ in range(warmup):
+            step(form)()
+        torch.cuda.synchronize()
+        hlb.profile_reset()
+        hlb.set_option(hlb.OPT_PROFILE, 1)
+        s = _time_steps(step(form), steps, 0)
+        hlb.set_option(hlb.OPT_PROFILE, 0)
+        prof = {n: hlb.profile_read(n) for n in names}
+        hlb.profile_reset()
+        return s, {n: (c, t / max(c, 1)) for n, (c, t) in prof.items()}
 
+    def roofline(kernel, launches, ms, ops):
+        tops = ops / (ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": tops, "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
+                "frac": tops / INT8_PEAK_TOPS, "traffic": measured_traffic(kernel, d, L),
+                "kernel": TRAFFIC[kernel]["match"], "avg_launch_ms": ms, "launches": launches,
+                "ops_per_launch": ops, "op": "int8 MAC x 2"}
+
+    # Headline: the multimodular INT8 form (Strategy 3; D int8 products per mod-q MAC)
+    cplan = hlb.plan(1, d, max(w.primes), w.p_absmax, "int8_crt")
+    s_crt, kc = timed("int8_crt", ("crt_gemm", "crt_split_p", "crt_split_x", "crt_combine"), args.steps,
+                      args.warmup)
+    c_ops = 2.0 * cplan["p_limbs"] * macs
     out = {
         "metric": METRIC,
-        "value": macs / s_int8,
+        "value": macs / s_crt,
         "unit": "mod-q MAC/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": s_int8 * 1e3,
+        "ms_per_step": s_crt * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "i8", "data": "synthetic",
         "config": {"workload": f"cp_mm d={d}: {d}x{d} plaintext (|P|<=2^20) times {d}x{d} a- and "
-                               f"b-parts over {L} RNS primes of {args.bits} bits, INT8-limb form",
-                   "m": d, "k": d, "n": d, "primes": L, "prime_bits": args.bits, "form": "int8",
-                   "digits": [plan["p_limbs"], plan["x_limbs"]]},
-        "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": INT8_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tops / INT8_PEAK_TOPS,
-                     "traffic": measured_traffic(d, L),
-                     "kernel": "gemm_i8_kernel", "avg_launch_ms": gemm_ms, "launches": n_gemm,
-                     "ops_per_launch": ops, "op": "int8 MAC x 2"},
-        "kernels_ms": {"gemm_i8": gemm_ms, "split_p": ms_sp / max(n_sp, 1),
-                       "split_x_per_matrix": ms_sx / max(n_sx, 1)},
+                               f"b-parts over {L} RNS primes of {args.bits} bits, INT8-limb form "
+                               f"(multimodular: {cplan['p_limbs']} int8 products per mod-q MAC)",
+                   "m": d, "k": d, "n": d, "primes": L, "prime_bits": args.bits, "form": "int8_crt",
+                   "moduli": cplan["p_limbs"]},
+        "roofline": roofline("crt_gemm", kc["crt_gemm"][0], kc["crt_gemm"][1], c_ops),
+        "kernels_ms": {n: v[1] for n, v in kc.items()},
     }
 
-    if not args.no_crt:
-        # multimodular INT8 form (Strategy 3): D int8 products instead of the digit pairs
-        for _ in range(args.warmup):
-            step("int8_crt")()
-        torch.cuda.synchronize()
-        hlb.profile_reset()
-        hlb.set_option(hlb.OPT_PROFILE, 1)
-        s_crt = _time_steps(step("int8_crt"), args.steps, 0)
-        hlb.set_option(hlb.OPT_PROFILE, 0)
-        prof = {name: hlb.profile_read(name) for name in ("crt_gemm", "crt_split_p", "crt_split_x", "crt_combine")}
-        hlb.profile_reset()
-        cplan = hlb.plan(1, d, max(w.primes), w.p_absmax, "int8_crt")
-        # the narrower GEMM tile, for comparison
-        hlb.set_option(hlb.OPT_CRT_WIDE, 0)
-        step("int8_crt")()
-        torch.cuda.synchronize()
-        hlb.set_option(hlb.OPT_PROFILE, 1)
-        _time_steps(step("int8_crt"), max(2, args.steps // 3), 0)
-        hlb.set_option(hlb.OPT_PROFILE, 0)
-        hlb.set_option(hlb.OPT_CRT_WIDE, 1)
-        n_narrow, t_narrow = hlb.profile_read("crt_gemm")
-        hlb.profile_reset()
-        c_ms = prof["crt_gemm"][1] / max(prof["crt_gemm"][0], 1)
-        c_ops = 2.0 * cplan["p_limbs"] * macs
-        out["int8_crt_form"] = {
-            "value": macs / s_crt, "unit": "mod-q MAC/s", "ms_per_step": s_crt * 1e3, "moduli": cplan["p_limbs"],
-            "gemm_ms": c_ms, "gemm_tops": c_ops / (c_ms * 1e-3) / 1e12,
-            "gemm_frac_of_int8_peak": c_ops / (c_ms * 1e-3) / 1e12 / INT8_PEAK_TOPS,
-            "kernels_ms": {n: t / max(c, 1) for n, (c, t) in prof.items()},
-            "gemm_ms_256x128_tile": t_narrow / max(n_narrow, 1)}
+    # The digit INT8 form (Strategy 1: 3 x 7 digit products per mod-q MAC)
+    if not args.no_digit:
+        dplan = hlb.plan(1, d, max(w.primes), w.p_absmax, "int8")
+        s_dig, kd = timed("int8", ("gemm_i8", "split_p", "split_x"), args.steps, args.warmup)
+        d_ops = 2.0 * dplan["p_limbs"] * dplan["x_limbs"] * macs
+        out["int8_digit_form"] = {
+            "value": macs / s_dig, "unit": "mod-q MAC/s", "ms_per_step": s_dig * 1e3,
+            "digits": [dplan["p_limbs"], dplan["x_limbs"]],
+            "roofline": roofline("gemm_i8", kd["gemm_i8"][0], kd["gemm_i8"][1], d_ops),
+            "kernels_ms": {n: v[1] for n, v in kd.items()}}
 
     if not args.no_fp64:
         fp_steps = max(2, args.steps // 3)
@@ -392,8 +386,10 @@ def main():
                             "gemm_tflops": f_tf, "gemm_frac_of_fp64_peak": f_tf / FP64_PEAK_TFLOPS}
         out["fp64_gemm"] = {"ms": s_dgemm * 1e3, "tflops": 2.0 * d ** 3 / s_dgemm / 1e12,
                             "shape": f"{d}x{d}x{d}", "impl": "torch.matmul float64"}
-        out["int8_vs_fp64_form_speedup"] = s_fp64 / s_int8
-        out["slowdown_vs_fp64_gemm"] = {"int8_form": s_int8 / s_dgemm, "fp64_form": s_fp64 / s_dgemm}
+        out["int8_vs_fp64_form_speedup"] = s_fp64 / s_crt
+        out["slowdown_vs_fp64_gemm"] = {"int8_form": s_crt / s_dgemm, "fp64_form": s_fp64 / s_dgemm}
+        if "int8_digit_form" in out:
+            out["slowdown_vs_fp64_gemm"]["int8_digit_form"] = s_dig / s_dgemm
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)

@@ -136,8 +136,44 @@ __device__ __forceinline__ void wait_vmcnt(int n) {
         case 12: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
         case 13: asm volatile("s_waitcnt vmcnt(13)" ::: "memory"); break;
         case 14: asm volatile("s_waitcnt vmcnt(14)" ::: "memory"); break;
+        case 15: asm volatile("s_waitcnt vmcnt(15)" ::: "memory"); break;
+        case 16: asm volatile("s_waitcnt vmcnt(16)" ::: "memory"); break;
+        case 17: asm volatile("s_waitcnt vmcnt(17)" ::: "memory"); break;
+        case 18: asm volatile("s_waitcnt vmcnt(18)" ::: "memory"); break;
+        case 19: asm volatile("s_waitcnt vmcnt(19)" ::: "memory"); break;
+        case 20: asm volatile("s_waitcnt vmcnt(20)" ::: "memory"); break;
+        case 21: asm volatile("s_waitcnt vmcnt(21)" ::: "memory"); break;
+        case 22: asm volatile("s_waitcnt vmcnt(22)" ::: "memory"); break;
+        case 23: asm volatile("s_waitcnt vmcnt(23)" ::: "memory"); break;
+        case 24: asm volatile("s_waitcnt vmcnt(24)" ::: "memory"); break;
+        case 25: asm volatile("s_waitcnt vmcnt(25)" ::: "memory"); break;
+        case 26: asm volatile("s_waitcnt vmcnt(26)" ::: "memory"); break;
+        case 27: asm volatile("s_waitcnt vmcnt(27)" ::: "memory"); break;
+        case 28: asm volatile("s_waitcnt vmcnt(28)" ::: "memory"); break;
+        case 29: asm volatile("s_waitcnt vmcnt(29)" ::: "memory"); break;
+        case 30: asm volatile("s_waitcnt vmcnt(30)" ::: "memory"); break;
         default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
     }
+}
+
+// Scheduling hint for the code just before it: alternate one MFMA with one LDS read, N times,
+// so the fragment reads of the next K half spread over the MFMAs of the current one instead
+// of bunching at the start (mask 0x008 = MFMA, 0x100 = DS read).
+template <int N>
+__device__ __forceinline__ void interleave_reads_with_mfmas() {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+}
+
+// s_waitcnt lgkmcnt(0) that stays after the MFMAs issued before it: an inline-asm wait does
+// not order MFMAs (they touch no memory), so without the scheduling barrier the compiler may
+// hoist it above them and stall on the LDS reads with the matrix pipe idle.
+__device__ __forceinline__ void wait_lds_after_mfmas() {
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
 // Workgroup barrier WITHOUT the memory fence of __syncthreads(): that fence waits for every

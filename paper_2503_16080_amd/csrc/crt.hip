@@ -5,7 +5,7 @@
 // every modular product is one exact INT8 -> INT32 matrix product:
 //   1. split: the centred operands (plaintext as signed integers; residues x mod q taken in
 //      (-q/2, q/2]) become D planes of balanced residues modulo p_0 .. p_{D-1} <= 256, in the
-//      tile-major, swizzled layout of the digit split;
+//      tile-major, swizzled layout of the digit split ([tile][k block][plane][128][64]);
 //   2. GEMM: one plain INT8 product per modulus and output tile (v_mfma_i32_32x32x32_i8,
 //      64 x 64 outputs per wave), |c| <= k 2^14 < 2^31; the epilogue writes the byte
 //      y_i = c * (M / p_i)^{-1} mod p_i;
@@ -16,7 +16,6 @@
 #include "common.hpp"
 #include "crt.hpp"
 #include "launch.hpp"
-#include "split.hpp"
 
 namespace hlb {
 
@@ -24,50 +23,76 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------------------
-// 1. Residue split
+// 1. Residue split, straight from registers to the workspace (no LDS): one thread owns one
+//    16-byte chunk (16 consecutive K) of one row of a 128-row tile -- a row of P, or a
+//    column of X -- and writes that chunk of every plane at its swizzled position.  Lanes
+//    run over the 4 chunks of a row first, so each 4 lanes store one contiguous 64-byte row.
+//    Values are taken as signed integers (qc = 0) or as residues modulo qc in their centred
+//    representatives; entries outside the valid range become zero.
 // ---------------------------------------------------------------------------------------
-// Converter for split_rows_tile / split_cols_tile: the value is taken as a signed integer
-// (qc = 0) or as a residue modulo qc in its centred representative, and plane i receives its
-// balanced residue modulo kCrtModuli[i].
-template <int D>
-struct CrtConv {
-    uint64_t qc;
-    __device__ __forceinline__ void operator()(const uint64_t (&x)[4], uint32_t (&out)[D]) const {
-        double v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int64_t s = (int64_t)x[e];
-            if (qc != 0 && 2 * x[e] > qc) s = (int64_t)x[e] - (int64_t)qc;
-            v[e] = (double)s;
-        }
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            uint32_t w = 0;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) w |= ((uint32_t)balanced_residue(v[e], kCrtModuli[i]) & 0xffu) << (8 * e);
-            out[i] = w;
-        }
-    }
-};
-
 constexpr int kCrtR = 128;  // rows (columns) per split tile
 
 template <int D>
-__global__ __launch_bounds__(kThreads) void crt_split_rows(const int64_t *__restrict__ P, int64_t ldp, int64_t m,
-                                                           int64_t k, int kblocks, uint64_t qc,
-                                                           int8_t *__restrict__ out) {
-    __shared__ uint8_t lds[D * kCrtR * kSplitRowPad];
-    split_rows_tile<D, kCrtR>(P, ldp, m, k, kblocks, blockIdx.x / kblocks, blockIdx.x % kblocks, out, lds,
-                              CrtConv<D>{qc});
+__device__ __forceinline__ void crt_store_chunk(const double (&v)[16], int8_t *blk, int r, int c) {
+    // blk: the [D][128][64] block of this (tile, k block); row r, logical chunk c
+    int8_t *dst = blk + r * 64 + ((c ^ swz(r)) << 4);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        uint32_t w[4];
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                x |= ((uint32_t)balanced_residue(v[q4 * 4 + e], kCrtModuli[i]) & 0xffu) << (8 * e);
+            w[q4] = x;
+        }
+        *(uint4 *)(dst + i * kCrtR * 64) = uint4{w[0], w[1], w[2], w[3]};
+    }
+}
+
+__device__ __forceinline__ double crt_centred(uint64_t x, uint64_t qc) {
+    const int64_t s = (qc != 0 && 2 * x > qc) ? (int64_t)x - (int64_t)qc : (int64_t)x;
+    return (double)s;
+}
+
+// grid: (tiles * kblocks) workgroups of 512 threads = 128 rows x 4 chunks
+template <int D>
+__global__ __launch_bounds__(512) void crt_split_rows(const int64_t *__restrict__ P, int64_t ldp, int64_t m,
+                                                      int64_t k, int kblocks, uint64_t qc, int8_t *__restrict__ out) {
+    const int tile = blockIdx.x / kblocks, kb = blockIdx.x % kblocks;
+    const int r = threadIdx.x >> 2, c = threadIdx.x & 3;
+    const int64_t row = (int64_t)tile * kCrtR + r;
+    const int64_t k0 = (int64_t)kb * kBK8 + c * 16;
+    const int64_t rc = row < m ? row : m - 1;
+    uint64_t x[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = (uint64_t)P[rc * ldp + (k0 + e < k ? k0 + e : k - 1)];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) asm volatile("" : "+v"(x[e]));  // all loads issued before the masks
+    double v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = (row < m && k0 + e < k) ? crt_centred(x[e], qc) : 0.0;
+    crt_store_chunk<D>(v, out + ((int64_t)tile * kblocks + kb) * (D * kCrtR * kBK8), r, c);
 }
 
 template <int D>
-__global__ __launch_bounds__(kThreads) void crt_split_cols(const uint64_t *__restrict__ X, int64_t ldx, int64_t k,
-                                                           int64_t n, int kblocks, uint64_t qc,
-                                                           int8_t *__restrict__ out) {
-    __shared__ uint8_t lds[D * kCrtR * kSplitRowPad];
-    split_cols_tile<D, kCrtR>(X, ldx, k, n, kblocks, blockIdx.x / kblocks, blockIdx.x % kblocks, out, lds,
-                              CrtConv<D>{qc});
+__global__ __launch_bounds__(512) void crt_split_cols(const uint64_t *__restrict__ X, int64_t ldx, int64_t k,
+                                                      int64_t n, int kblocks, uint64_t qc, int8_t *__restrict__ out) {
+    const int tile = blockIdx.x / kblocks, kb = blockIdx.x % kblocks;
+    const int r = threadIdx.x >> 2, c = threadIdx.x & 3;
+    const int64_t col = (int64_t)tile * kCrtR + r;
+    const int64_t k0 = (int64_t)kb * kBK8 + c * 16;
+    const int64_t cc = col < n ? col : n - 1;
+    uint64_t x[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = X[(k0 + e < k ? k0 + e : k - 1) * ldx + cc];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) asm volatile("" : "+v"(x[e]));
+    double v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = (col < n && k0 + e < k) ? crt_centred(x[e], qc) : 0.0;
+    crt_store_chunk<D>(v, out + ((int64_t)tile * kblocks + kb) * (D * kCrtR * kBK8), r, c);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -76,13 +101,16 @@ __global__ __launch_bounds__(kThreads) void crt_split_cols(const uint64_t *__res
 // ---------------------------------------------------------------------------------------
 constexpr int kCrtBM = 256, kCrtWavesN = 2, kCrtThreads = 512;
 constexpr int kCrtSub = kCrtR * kBK8;  // bytes of one plane block (128 x 64)
-constexpr int kCrtNbuf = 3;
 
+// A stage holds only 2 NB MFMAs per wave, so several stages must be in flight to cover the
+// load latency: as many as fit in the 160 KB of LDS.
 template <int NB>
 struct CrtTile {
     static constexpr int BN = kCrtWavesN * NB * 32;
     static constexpr int XSUB = BN / kCrtR;            // residue plane blocks per stage
     static constexpr int STAGE = (2 + XSUB) * kCrtSub;  // two plaintext blocks + residue blocks
+    static constexpr int GROUP = 2;                      // stages per barrier
+    static constexpr int NBUF = (160 * 1024) / STAGE / GROUP * GROUP;
 };
 
 __device__ __forceinline__ uint8_t crt_y(int c, int p, int inv) {
@@ -101,6 +129,7 @@ __device__ __forceinline__ uint8_t crt_y(int c, int p, int inv) {
 template <int NB>
 __global__ __launch_bounds__(kCrtThreads, 1) void crt_gemm_kernel(const CrtGemmArgs args) {
     using T = CrtTile<NB>;
+    constexpr int kCrtNbuf = T::NBUF;
     __shared__ __attribute__((aligned(16))) int8_t lds[kCrtNbuf * T::STAGE];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -171,29 +200,45 @@ __global__ __launch_bounds__(kCrtThreads, 1) void crt_gemm_kernel(const CrtGemmA
                 acc[mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a[mb], f.b[nb], acc[mb][nb], 0, 0, 0);
     };
 
-    // Pipeline as in the digit GEMM: half a stage of fragments in registers, NBUF stages in LDS.
-    auto outstanding = [&](int need, int issued_hi) {
-        const int ahead = min(KB - 1, issued_hi) - need;
+    // Pipeline: half a stage of fragments in registers, NBUF stages in LDS, and one wait +
+    // barrier per group of G stages.  At a group's last half-stage each wave waits for its
+    // own loads of the whole next group, the barrier makes them visible (and tells that every
+    // wave has finished reading this group's buffers), and those buffers are refilled NBUF
+    // stages ahead.
+    constexpr int G = T::GROUP;
+    auto outstanding = [&](int need_hi, int issued_hi) {
+        const int ahead = min(KB - 1, issued_hi) - min(KB - 1, need_hi);
         return ahead > 0 ? ahead * loads_per_stage : 0;
     };
 #pragma unroll
     for (int st = 0; st < kCrtNbuf; ++st)
         if (st < KB) gload(st, st);
-    wait_vmcnt(outstanding(0, kCrtNbuf - 1));
+    wait_vmcnt(outstanding(G - 1, kCrtNbuf - 1));
     stage_barrier();
     Frags f0, f1;
     read_frags(f0, 0, 0);
 #pragma unroll 1
-    for (int kb = 0; kb < KB; ++kb) {
-        const int cur = kb % kCrtNbuf;
-        read_frags(f1, cur, 1);
-        mfmas(f0);
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        wait_vmcnt(outstanding(kb + 1, kb + kCrtNbuf - 1));
-        stage_barrier();
-        if (kb + kCrtNbuf < KB) gload(kb + kCrtNbuf, cur);
-        if (kb + 1 < KB) read_frags(f0, (kb + 1) % kCrtNbuf, 0);
-        mfmas(f1);
+    for (int kb = 0; kb < KB; kb += G) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int st = kb + g;
+            if (st >= KB) break;
+            const int cur = st % kCrtNbuf;
+            read_frags(f1, cur, 1);
+            mfmas(f0);
+            interleave_reads_with_mfmas<2 + NB>();
+            if (g == G - 1 || st + 1 == KB) {
+                wait_lds_after_mfmas();
+                // stages issued so far: up to kb + NBUF - 1; the next group must have landed
+                wait_vmcnt(outstanding(kb + 2 * G - 1, kb + kCrtNbuf - 1));
+                stage_barrier();
+#pragma unroll
+                for (int h = 0; h < G; ++h)
+                    if (kb + h + kCrtNbuf < KB) gload(kb + h + kCrtNbuf, (kb + h) % kCrtNbuf);
+            }
+            if (st + 1 < KB) read_frags(f0, (st + 1) % kCrtNbuf, 0);
+            mfmas(f1);
+        }
     }
 
     const int p = kCrtModuli[mi];
@@ -278,7 +323,7 @@ int crt_round_d(int D) {
 hipError_t launch_crt_split_rows(int D, const int64_t *P, int64_t ldp, int64_t m, int64_t k, int tiles, int kblocks,
                                  uint64_t qc, int8_t *out, hipStream_t s) {
     if (tiles <= 0 || kblocks <= 0) return hipSuccess;
-    const dim3 g(tiles * kblocks), b(kThreads);
+    const dim3 g(tiles * kblocks), b(512);
 #define HLB_CASE(DD) \
     if (D == DD) { hipLaunchKernelGGL(crt_split_rows<DD>, g, b, 0, s, P, ldp, m, k, kblocks, qc, out); return hipGetLastError(); }
     HLB_CRT_D(HLB_CASE)
@@ -289,7 +334,7 @@ hipError_t launch_crt_split_rows(int D, const int64_t *P, int64_t ldp, int64_t m
 hipError_t launch_crt_split_cols(int D, const uint64_t *X, int64_t ldx, int64_t k, int64_t n, int tiles, int kblocks,
                                  uint64_t qc, int8_t *out, hipStream_t s) {
     if (tiles <= 0 || kblocks <= 0) return hipSuccess;
-    const dim3 g(tiles * kblocks), b(kThreads);
+    const dim3 g(tiles * kblocks), b(512);
 #define HLB_CASE(DD) \
     if (D == DD) { hipLaunchKernelGGL(crt_split_cols<DD>, g, b, 0, s, X, ldx, k, n, kblocks, qc, out); return hipGetLastError(); }
     HLB_CRT_D(HLB_CASE)

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f64_planes_kernel(const Gemm
         mfmas(f1);
         read_frags(f1, cur, 3);
         mfmas(f0);
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        wait_lds_after_mfmas();
         wait_vmcnt(outstanding(kb + 1, kb + T::NBUF - 1));
         stage_barrier();
         if (kb + T::NBUF < KB) gload(kb + T::NBUF, cur);

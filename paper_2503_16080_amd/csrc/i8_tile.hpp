@@ -60,18 +60,6 @@ __device__ __forceinline__ uint64_t recombine_i8(const int (&c)[NS], uint64_t q,
     return r;
 }
 
-// Scheduling hint for the code just before it: alternate one MFMA with one LDS read, N times,
-// so the fragment reads of the next K half spread over the MFMAs of the current one instead
-// of bunching at the start (mask 0x008 = MFMA, 0x100 = DS read).
-template <int N>
-__device__ __forceinline__ void interleave_reads_with_mfmas() {
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-    }
-}
-
 // Everything one output tile needs.
 struct TileJob {
     const int8_t *gP;  // first K block of this tile row's plaintext digits
@@ -183,7 +171,7 @@ __device__ __forceinline__ void run_tile(const TileJob &job, int8_t *lds) {
         read_frags(f1, cur, 1);
         mfmas(f0);
         interleave_reads_with_mfmas<T::DP + T::DX - T::J0>();
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        wait_lds_after_mfmas();
         // stages issued so far: up to kb + NBUF - 1
         wait_vmcnt(outstanding(kb + 1, kb + NBUF - 1));
         stage_barrier();

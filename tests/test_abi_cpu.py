@@ -80,7 +80,13 @@ def test_plan_fp64_paper_form():
 
 
 def test_plan_auto_prefers_int8_and_forced_chunk():
-    assert hlb.plan(1, 4096, Q50, 1 << 20, "auto")["form"] == hlb.FORM_INT8
+    # AUTO takes the multimodular form when its moduli count is below 3/4 of the digit pairs
+    # (11 < 15.75 for a 20-bit plaintext and 50-bit primes), the digit form when that fails
+    # (k beyond the int32 bound of the multimodular products)
+    assert hlb.plan(1, 4096, Q50, 1 << 20, "auto")["form"] == hlb.FORM_INT8_CRT
+    assert hlb.plan(0, 4096, Q50, 1, "auto")["form"] == hlb.FORM_INT8_CRT
+    assert hlb.plan(1, 200000, Q50, 1 << 20, "auto")["form"] == hlb.FORM_INT8
+    assert hlb.plan(1, 4096, Q50, 1 << 51, "auto")["form"] == hlb.FORM_INT8_CRT   # 16 moduli vs 49 pairs
     try:
         hlb.set_option(hlb.OPT_FORCE_KCHUNK, 200)
         assert hlb.plan(1, 4096, Q50, 1 << 20, "int8")["k_chunk"] == 192
