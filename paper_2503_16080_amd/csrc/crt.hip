@@ -96,22 +96,30 @@ __global__ __launch_bounds__(512) void crt_split_cols(const uint64_t *__restrict
 }
 
 // ---------------------------------------------------------------------------------------
-// 2. One INT8 product per modulus: 8 waves (4 x 2) of 64 x (32 NB) outputs each, i.e. a
-//    256 x (64 NB) tile: NB = 2 (256 x 128) or NB = 4 (256 x 256, fewer operand bytes per MAC)
+// 2. One INT8 product per modulus on a 256 x BN output tile: WM x WN waves, each owning
+//    MB x NB blocks of 32 x 32 outputs (WM * MB * 32 = 256).  Variants (tile, waves, block
+//    per wave): 256 x 128 with 8 waves of 64 x 64; 256 x 256 with 8 waves of 64 x 128.
+//    (A wave of 128 x 128 would need 256 accumulator registers plus its fragments, more than
+//    the register file holds without spilling in the main loop.)
 // ---------------------------------------------------------------------------------------
-constexpr int kCrtBM = 256, kCrtWavesN = 2, kCrtThreads = 512;
+constexpr int kCrtBM = 256;
 constexpr int kCrtSub = kCrtR * kBK8;  // bytes of one plane block (128 x 64)
 
-// A stage holds only 2 NB MFMAs per wave, so several stages must be in flight to cover the
-// load latency: as many as fit in the 160 KB of LDS.
-template <int NB>
+// A stage holds only MB * NB MFMAs per wave and K half, so several stages must be in flight
+// to cover the load latency: as many as fit in the 160 KB of LDS.
+template <int MB_, int NB_, int WM_, int WN_>
 struct CrtTile {
-    static constexpr int BN = kCrtWavesN * NB * 32;
+    static constexpr int MB = MB_, NB = NB_, WM = WM_, WN = WN_;
+    static_assert(WM * MB * 32 == kCrtBM, "256 rows per tile");
+    static constexpr int THREADS = 64 * WM * WN;
+    static constexpr int BN = WN * NB * 32;
     static constexpr int XSUB = BN / kCrtR;            // residue plane blocks per stage
     static constexpr int STAGE = (2 + XSUB) * kCrtSub;  // two plaintext blocks + residue blocks
     static constexpr int GROUP = 2;                      // stages per barrier
     static constexpr int NBUF = (160 * 1024) / STAGE / GROUP * GROUP;
 };
+using CrtNarrow = CrtTile<2, 2, 4, 2>;
+using CrtWide = CrtTile<2, 4, 4, 2>;
 
 __device__ __forceinline__ uint8_t crt_y(int c, int p, int inv) {
     // (c mod p) * inv mod p, in [0, p); c and the products are exact in double
@@ -126,9 +134,9 @@ __device__ __forceinline__ uint8_t crt_y(int c, int p, int inv) {
     return (uint8_t)(int)y;
 }
 
-template <int NB>
-__global__ __launch_bounds__(kCrtThreads, 1) void crt_gemm_kernel(const CrtGemmArgs args) {
-    using T = CrtTile<NB>;
+template <class T>
+__global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_kernel(const CrtGemmArgs args) {
+    constexpr int MB = T::MB, NB = T::NB, kCrtThreads = T::THREADS, kCrtWavesN = T::WN;
     constexpr int kCrtNbuf = T::NBUF;
     __shared__ __attribute__((aligned(16))) int8_t lds[kCrtNbuf * T::STAGE];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -152,9 +160,9 @@ __global__ __launch_bounds__(kCrtThreads, 1) void crt_gemm_kernel(const CrtGemmA
     const int8_t *gP = args.Pd + (int64_t)(2 * rb) * tile_stride + (int64_t)mi * kCrtSub;
     const int8_t *gX = args.Xd + (int64_t)(cb * T::XSUB) * tile_stride + (int64_t)mi * kCrtSub;
 
-    v16i acc[2][NB];
+    v16i acc[MB][NB];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < MB; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[a][b] = v16i{0};
 
@@ -170,19 +178,20 @@ __global__ __launch_bounds__(kCrtThreads, 1) void crt_gemm_kernel(const CrtGemmA
     };
     const int loads_per_stage = (2 + T::XSUB) * loads_of_wave<kCrtThreads, CH>(wave_u);
 
-    // plaintext rows of this wave: block wm / 2, rows (wm % 2) * 64 + 32 mb + lane % 32;
+    // plaintext rows of this wave: wm * 32 MB + 32 mb + lane % 32, in 128-row block psub;
     // residue columns: wn * 32 NB + 32 nb + lane % 32, in block (that) / 128
-    const int psub = wm >> 1;
+    const int psub = (wm * 32 * MB) / kCrtR;
+    const int prow0 = (wm * 32 * MB) % kCrtR;
     struct Frags {
-        v4i a[2], b[NB];
+        v4i a[MB], b[NB];
     };
     auto read_frags = [&](Frags &f, int buf, int kk) {
         const int8_t *lp = lds + buf * T::STAGE + psub * kCrtSub;
         const int8_t *lx = lds + buf * T::STAGE + 2 * kCrtSub;
         const int c = kk * 2 + (lane >> 5);
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-            const int r = (wm & 1) * 64 + mb * 32 + (lane & 31);
+        for (int mb = 0; mb < MB; ++mb) {
+            const int r = prow0 + mb * 32 + (lane & 31);
             f.a[mb] = *(const v4i *)(lp + r * 64 + ((c ^ swz(r)) << 4));
         }
 #pragma unroll
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(kCrtThreads, 1) void crt_gemm_kernel(const CrtGemmA
     };
     auto mfmas = [&](const Frags &f) {
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
                 acc[mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a[mb], f.b[nb], acc[mb][nb], 0, 0, 0);
@@ -226,7 +235,7 @@ __global__ __launch_bounds__(kCrtThreads, 1) void crt_gemm_kernel(const CrtGemmA
             const int cur = st % kCrtNbuf;
             read_frags(f1, cur, 1);
             mfmas(f0);
-            interleave_reads_with_mfmas<2 + NB>();
+            interleave_reads_with_mfmas<MB + NB>();
             if (g == G - 1 || st + 1 == KB) {
                 wait_lds_after_mfmas();
                 // stages issued so far: up to kb + NBUF - 1; the next group must have landed
@@ -243,11 +252,11 @@ __global__ __launch_bounds__(kCrtThreads, 1) void crt_gemm_kernel(const CrtGemmA
 
     const int p = kCrtModuli[mi];
     const int inv = args.inv[mi];
-    const int64_t m0 = (int64_t)rb * kCrtBM + wm * 64;
+    const int64_t m0 = (int64_t)rb * kCrtBM + wm * 32 * MB;
     const int64_t n0 = (int64_t)(cb - sg.tile_begin) * T::BN + wn * 32 * NB;
     uint8_t *Y = sg.Y + (int64_t)mi * args.m * sg.ldy;
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
@@ -342,15 +351,19 @@ hipError_t launch_crt_split_cols(int D, const uint64_t *X, int64_t ldx, int64_t 
     return hipErrorInvalidValue;
 }
 
-int crt_tile_cols(int wide) { return wide ? CrtTile<4>::BN : CrtTile<2>::BN; }
+int crt_tile_cols(int variant) { return variant == 0 ? CrtNarrow::BN : CrtWide::BN; }
 
-hipError_t launch_crt_gemm(int wide, const CrtGemmArgs &a, hipStream_t s) {
+template <class T>
+static hipError_t launch_crt_t(int64_t grid, const CrtGemmArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(crt_gemm_kernel<T>, dim3((unsigned)grid), dim3(T::THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_crt_gemm(int variant, const CrtGemmArgs &a, hipStream_t s) {
     const int64_t grid = (int64_t)a.D * a.tiles_m * a.tiles_n;
     if (grid <= 0) return hipSuccess;
     if (grid > INT32_MAX) return hipErrorInvalidValue;
-    if (wide) hipLaunchKernelGGL(crt_gemm_kernel<4>, dim3((unsigned)grid), dim3(kCrtThreads), 0, s, a);
-    else hipLaunchKernelGGL(crt_gemm_kernel<2>, dim3((unsigned)grid), dim3(kCrtThreads), 0, s, a);
-    return hipGetLastError();
+    return variant == 0 ? launch_crt_t<CrtNarrow>(grid, a, s) : launch_crt_t<CrtWide>(grid, a, s);
 }
 
 hipError_t launch_crt_combine(const CrtCombineArgs &a, hipStream_t s) {

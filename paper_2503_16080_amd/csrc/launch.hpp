@@ -58,9 +58,10 @@ hipError_t launch_crt_split_cols(int D, const uint64_t *X, int64_t ldx, int64_t 
                                  uint64_t qc, int8_t *out, hipStream_t s);
 struct CrtGemmArgs;
 struct CrtCombineArgs;
-// wide = 0: 256 x 128 output tiles; 1: 256 x 256.  crt_tile_cols gives the tile width.
-int crt_tile_cols(int wide);
-hipError_t launch_crt_gemm(int wide, const CrtGemmArgs &a, hipStream_t s);
+// variant 0: 256 x 128 output tiles; 1: 256 x 256 (both 8 waves).  crt_tile_cols gives the
+// tile width.
+int crt_tile_cols(int variant);
+hipError_t launch_crt_gemm(int variant, const CrtGemmArgs &a, hipStream_t s);
 hipError_t launch_crt_combine(const CrtCombineArgs &a, hipStream_t s);
 
 // Auxiliary kernels.
