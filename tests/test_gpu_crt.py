@@ -52,11 +52,13 @@ def test_cp_mm_crt_45_bit_and_measured_bound():
     assert np.array_equal(_np(PA), wantA) and np.array_equal(_np(PB), wantB)
 
 
-@pytest.mark.parametrize("q", [2, 3, 97, 65537, (1 << 31) - 1, (1 << 52) - 47])
-def test_mod_pp_mm_crt_moduli(q):
-    # both operands full residues: the widest moduli sets
+@pytest.mark.parametrize("q,D", [(2, 8), (3, 8), (97, 8), (65537, 8), ((1 << 31) - 1, 10), ((1 << 40) + 15, 12),
+                                 ((1 << 45) + 59, 14), ((1 << 52) - 47, 16)])
+def test_mod_pp_mm_crt_moduli(q, D):
+    # both operands full residues: every instantiated moduli count
     g = wl.rng(q % 1000)
     m, k, n = 70, 200, 90
+    assert hlb.plan(0, k, q, 1, "int8_crt")["p_limbs"] == D
     P = g.integers(0, q, size=(m, k), dtype=np.uint64)
     X = g.integers(0, q, size=(k, n), dtype=np.uint64)
     got = _np(hlb.mod_pp_mm(q, _t(P), _t(X), form="int8_crt"))

@@ -35,7 +35,8 @@ def _check_large(w, PA, PB, rows, vectors=2, seed=0):
                 assert np.array_equal(lhs, oracle.matvec_mod(q, C, r)), (i, nm, "Freivalds")
 
 
-@pytest.mark.parametrize("d,form", [(4096, "fp64"), (4096, "int8"), (8192, "int8"), (8192, "fp64")])
+@pytest.mark.parametrize("d,form", [(4096, "fp64"), (4096, "int8"), (4096, "int8_crt"), (8192, "int8_crt"),
+                                    (8192, "int8"), (8192, "fp64")])
 def test_cp_mm_benchmark_size(d, form):
     print(f"\n[large] d={d} form={form}", flush=True)
     w = wl.cpmm_uniform(1000 + d, d, d, d, 50, 3)
