@@ -4,12 +4,14 @@
  *
  * The library evaluates the reduction of CP-MM to modular plaintext matrix products
  * (Mod-PP-MM) over each RNS prime (Algorithm alg:pcmm step 1; Theorems th:pcmm and
- * th:pcmm-shs), and evaluates every Mod-PP-MM exactly as matrix products of small limbs
- * followed by an integer recombination and a reduction modulo q (Section 6.1, Strategy 1,
- * Lemma le:strategy1 and Eq decomp).  Two limb forms are provided:
- *   HLB_FORM_INT8  balanced signed 8-bit digits multiplied on the INT8->INT32 matrix cores,
- *   HLB_FORM_FP64  17..26-bit limbs multiplied on the FP64 matrix cores (the paper's form).
- * Both produce the unique canonical result in [0, q) -- bit-identical to each other.
+ * th:pcmm-shs), and evaluates every Mod-PP-MM exactly, in one of three forms (Section 6.1):
+ *   HLB_FORM_INT8_CRT  Strategy 3 (FLINT variant): the centred integer product modulo small
+ *                      coprime moduli <= 256, one INT8->INT32 matrix product each, then the CRT;
+ *   HLB_FORM_INT8      Strategy 1 with balanced signed 8-bit digits on the INT8 matrix cores;
+ *   HLB_FORM_FP64      Strategy 1 with 17..26-bit limbs on the FP64 matrix cores (the
+ *                      paper's form).
+ * All produce the unique canonical result in [0, q) -- bit-identical to each other.
+ * hlb_cp_mm_trunc_b adds Strategy 2 (an approximate b-part) over one modulus.
  *
  * Orientation.  The paper multiplies an encrypted matrix on the right, M * U.  This ABI takes
  * the plaintext on the LEFT, C = P * X, which is the same computation on transposed
@@ -26,8 +28,9 @@
  *    Argument and planning errors are reported synchronously, before anything is enqueued.
  *    Entry points documented as "synchronous" synchronise `stream` before returning.
  *  - Moduli: 2 <= q < 2^52.
- *  - Workspace (digit planes for the INT8 form) is allocated by the library from a
- *    stream-ordered pool and freed in stream order; hlb_release() returns pooled memory.
+ *  - Workspace (digit or residue planes, the multimodular bytes, FP64 double planes) is
+ *    allocated by the library from a stream-ordered pool and freed in stream order;
+ *    hlb_release() returns pooled memory.
  *  - Calls on different streams may run concurrently.
  *  - The functions are not re-entrant during hlb_release().
  */
@@ -51,7 +54,8 @@ typedef enum {
 } hlb_status;
 
 typedef enum {
-    HLB_FORM_AUTO = 0,     /* INT8 where a plan exists, else FP64 */
+    HLB_FORM_AUTO = 0,     /* multimodular where it needs under 3/4 of the digit products
+                              (and m, n >= 256), else INT8 digits, else FP64 */
     HLB_FORM_FP64 = 1,     /* FP64 limbs on v_mfma_f64_16x16x4_f64 */
     HLB_FORM_INT8 = 2,     /* balanced int8 digits on v_mfma_i32_32x32x32_i8 (Strategy 1) */
     HLB_FORM_INT8_CRT = 3  /* multimodular: the centred integer product modulo D coprime
@@ -196,17 +200,22 @@ hlb_status hlb_plaintext_absmax(const int64_t *P, int64_t m, int64_t k, int64_t 
                                 int64_t *absmax, void *stream);
 
 /*
- * Limb plan the library would use (host only, no device work).  Exactness rule (Lemma
- * le:strategy1): every partial sum of limb products must stay below 2^31 in magnitude
- * (INT8 form, int32 accumulators) or 2^53 (FP64 form), so the plan fixes the limb counts
- * and the number of K steps accumulated before a fold into a 64-bit residue.
+ * Plan the library would use (host only, no device work).
+ *   Limb forms (Lemma le:strategy1): every partial sum of limb products must stay below 2^31
+ *   in magnitude (INT8 digits, int32 accumulators) or 2^53 (FP64), so the plan fixes the
+ *   limb counts and the number of K steps accumulated before a fold into a 64-bit residue.
+ *   Multimodular form (Strategy 3): p_limbs = x_limbs = D, the number of moduli; their
+ *   product is at least 4 k a floor(q/2) (a = p_absmax, or floor(q/2) for kind 0), and
+ *   k <= 131071 keeps each modular product exact in int32.
  *   kind: 0 = Mod-PP-MM (P is a residue < q), 1 = CP-MM (|P| <= p_absmax).
+ *   With HLB_FORM_AUTO the plan depends on k only; the product entry points also fall
+ *   back from the multimodular to the digit form when m or n is below 256.
  */
 typedef struct {
-    int form;          /* HLB_FORM_INT8 or HLB_FORM_FP64 */
-    int p_limbs;       /* limbs (digits) of the left operand */
-    int x_limbs;       /* limbs (digits) of the right operand */
-    int shifts;        /* accumulators per output = p_limbs + x_limbs - 1 */
+    int form;          /* HLB_FORM_INT8, HLB_FORM_INT8_CRT or HLB_FORM_FP64 */
+    int p_limbs;       /* limbs (digits) of the left operand; multimodular: moduli */
+    int x_limbs;       /* limbs (digits) of the right operand; multimodular: moduli */
+    int shifts;        /* accumulators per output = p_limbs + x_limbs - 1 (limb forms) */
     int limb_bits;     /* bits per limb: 8 (INT8) or w (FP64) */
     int max_pairs;     /* largest number of limb products sharing one accumulator */
     int64_t k_chunk;   /* K elements accumulated before a fold (>= k means no fold) */

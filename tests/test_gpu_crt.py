@@ -131,3 +131,44 @@ def test_crt_large_sampled_rows_and_forms_agree():
     for l in range(2):
         assert np.array_equal(out["int8_crt"][0][l][rows], wantA[l][rows])
         assert np.array_equal(out["int8_crt"][1][l][rows], wantB[l][rows])
+
+
+def test_auto_picks_form_by_shape():
+    # AUTO: the multimodular GEMM for products of at least 256 x 256 outputs, the digit GEMM
+    # below that (the kernels that ran are visible in the profiling records)
+    w = wl.cpmm_uniform(5500, 512, 300, 512, 50, 1)
+    small = wl.cpmm_uniform(5501, 100, 300, 80, 50, 1)
+    ran = {}
+    try:
+        for name, case in (("big", w), ("small", small)):
+            hlb.profile_reset()
+            hlb.set_option(hlb.OPT_PROFILE, 1)
+            PA, PB = hlb.cp_mm(_t(case.P), _t(case.A), _t(case.B), case.primes, p_absmax=case.p_absmax, form="auto")
+            torch.cuda.synchronize()
+            hlb.set_option(hlb.OPT_PROFILE, 0)
+            ran[name] = {k: hlb.profile_read(k)[0] for k in ("crt_gemm", "gemm_i8")}
+            want = oracle.cp_mm(case.P, case.A, case.B, case.primes)
+            assert np.array_equal(_np(PA), want[0]) and np.array_equal(_np(PB), want[1])
+    finally:
+        hlb.set_option(hlb.OPT_PROFILE, 0)
+        hlb.profile_reset()
+    assert ran["big"] == {"crt_gemm": 1, "gemm_i8": 0}
+    assert ran["small"] == {"crt_gemm": 0, "gemm_i8": 1}
+
+
+def test_batch_in_multimodular_form():
+    # a batch in the multimodular form runs problem by problem; results as for the oracle
+    primes = wl.ntt_primes(45, 2)
+    g = wl.rng(5600)
+    probs, want = [], []
+    for m, k, n in ((300, 200, 260), (64, 128, 96), (257, 513, 300)):
+        P = wl.plaintext_matrix(g, m, k)
+        A = np.stack([wl.uniform_residues(g, (k, n), q) for q in primes])
+        B = np.stack([wl.uniform_residues(g, (k, n), q) for q in primes])
+        probs.append(dict(P=_t(P), A=_t(A), B=_t(B), p_absmax=1 << 20,
+                          PA=torch.empty((2, m, n), dtype=torch.int64, device=DEV),
+                          PB=torch.empty((2, m, n), dtype=torch.int64, device=DEV)))
+        want.append(oracle.cp_mm(P, A, B, primes))
+    hlb.cp_mm_batch(probs, primes, form="int8_crt")
+    for p, (wA, wB) in zip(probs, want):
+        assert np.array_equal(_np(p["PA"]), wA) and np.array_equal(_np(p["PB"]), wB)
