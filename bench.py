@@ -48,7 +48,10 @@ def _parse():
                          "shapes over 4 primes of 45 bits; trunc: the CP-MM of size --d with "
                          "the b-part truncated (Strategy 2) next to the exact one")
     ap.add_argument("--b-err-log2", type=float, default=45.0,
-                    help="trunc workload: error budget of the b-part (log2)")
+                    help="trunc workload: error budget of the FP64 b-part (log2)")
+    ap.add_argument("--b-err-log2-int8", type=float, default=36.5,
+                    help="trunc workload: error budget of the INT8 b-part (log2); the default drops "
+                         "2 digit shifts, the most that keeps the precision within a bit of exact")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the counter summary from two rocprofv3 --pmc output directories "
                          "(FETCH_SIZE run, WRITE_SIZE run) and exit")
@@ -225,9 +228,9 @@ def run_trunc(args):
     PA = torch.empty((L, d, d), dtype=torch.int64, device=dev)
     PB = torch.empty((L, d, d), dtype=torch.int64, device=dev)
     macs = 2 * L * d * d * d
-    budget = args.b_err_log2
     res = {}
     for form in ("int8", "fp64"):
+        budget = args.b_err_log2_int8 if form == "int8" else args.b_err_log2
         steps = args.steps if form == "int8" else max(2, args.steps // 3)
         warm = args.warmup if form == "int8" else 1
         plan = hlb.plan_trunc_b(d, min(w.primes), max(w.primes), w.p_absmax, budget, form)
@@ -242,7 +245,7 @@ def run_trunc(args):
         kname = "gemm_i8_trunc" if form == "int8" else "gemm_f64_trunc"
         n_k, ms_k = hlb.profile_read(kname)
         hlb.profile_reset()
-        res[form] = {"exact_ms": s_exact * 1e3, "trunc_ms": s_trunc * 1e3,
+        res[form] = {"b_err_log2": budget, "exact_ms": s_exact * 1e3, "trunc_ms": s_trunc * 1e3,
                      "trunc_value": macs / s_trunc, "exact_value": macs / s_exact,
                      "b_part_products": plan["products"], "dropped_shifts": plan["dropped_shifts"],
                      "b_err_bound_log2": plan["err_bound_log2"],
@@ -253,15 +256,57 @@ def run_trunc(args):
     s_dgemm = _time_steps(lambda: torch.matmul(Xf, Yf, out=Zf), max(3, args.steps // 2), 2)
     for form in res:
         res[form]["slowdown_vs_fp64_gemm"] = res[form]["trunc_ms"] / (s_dgemm * 1e3)
+    del Xf, Yf, Zf, P, A, B, PA, PB
+    precision = trunc_precision(d, w.primes[0], args.b_err_log2,
+                                sorted({args.b_err_log2, args.b_err_log2_int8, 28.0}, reverse=True))
     print(json.dumps({
         "metric": f"CP-MM mod-q MACs/s at d={d} with the b-part truncated (Strategy 2)",
         "value": res["int8"]["trunc_value"], "unit": "mod-q MAC/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": res["int8"]["trunc_ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
         "config": {"workload": f"cp_mm d={d} over one modulus of {args.bits} bits, a-part exact, "
-                               f"b-part error <= 2^{budget:g}", "b_err_log2": budget},
-        "forms": res, "fp64_gemm_ms": s_dgemm * 1e3,
+                               f"b-part error <= 2^{args.b_err_log2_int8:g} (INT8), "
+                               f"2^{args.b_err_log2:g} (FP64)"},
+        "forms": res, "fp64_gemm_ms": s_dgemm * 1e3, "precision_bits": precision,
     }), flush=True)
+
+
+def trunc_precision(d, q, budget_fp64, budgets_int8):
+    """The paper's precision metric (Section 6: -log2 of the largest entry error of the
+    decrypted, decoded product against the cleartext product U M) for the exact CP-MM and
+    the truncated b-parts, on a real encryption under one modulus q built on the GPU:
+    B = -A S + round(2^15 M) + E, P = round(2^20 U), M and U uniform in [-1, 1], S ternary,
+    E rounded Gaussian (sigma 3.2).  |P (round(2^15 M) + E)| stays below q/2, so the centred
+    decryption needs no wrap."""
+    import torch
+
+    import paper_2503_16080_amd as hlb
+
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(2025)
+    dm, dp = 15, 20
+    M = torch.rand((d, d), dtype=torch.float64, device=dev, generator=g) * 2 - 1
+    U = torch.rand((d, d), dtype=torch.float64, device=dev, generator=g) * 2 - 1
+    S = torch.randint(-1, 2, (d, d), dtype=torch.int64, device=dev, generator=g)
+    E = torch.floor(torch.randn((d, d), dtype=torch.float64, device=dev, generator=g) * 3.2 + 0.5).to(torch.int64)
+    A = torch.randint(0, q, (1, d, d), dtype=torch.int64, device=dev, generator=g)
+    P = torch.floor(U * 2.0 ** dp + 0.5).to(torch.int64)
+    B = hlb.hlb_test_encrypt(A, S, hlb.hlb_test_encode(M, 2.0 ** dm) + E, [q])
+    want = torch.matmul(U, M)
+
+    def bits(PA, PB):
+        D = hlb.hlb_test_decrypt(PA, PB, S, [q])[0]
+        Dc = torch.where(D > q // 2, D - q, D).to(torch.float64) / 2.0 ** (dm + dp)
+        return float(-torch.log2((Dc - want).abs().max()))
+
+    out = {"exact": bits(*hlb.cp_mm(P, A, B, [q], p_absmax=1 << dp, form="auto"))}
+    for form, budgets in (("fp64", (budget_fp64,)), ("int8", budgets_int8)):
+        for b in budgets:
+            plan = hlb.plan_trunc_b(d, q, q, 1 << dp, b, form)
+            key = f"{form}_b{b:g}" + (f"_drop{plan['dropped_shifts']}" if form == "int8" else "")
+            out[key] = bits(*hlb.cp_mm_trunc_b(P, A, B, [q], b, p_absmax=1 << dp, form=form))
+    return out
 
 
 def main():
