@@ -425,7 +425,8 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
         tg_n[i] = (rights[i].n + bn - 1) / bn;
         t128_n[i] = tg_n[i] * xsub;
         tn_total += t128_n[i];
-        ybytes += (int64_t)D * mmax * ((rights[i].n + 15) / 16 * 16);
+        // product planes cover whole GEMM tiles (layout of CrtSeg)
+        ybytes += (int64_t)D * (t128_m / 2 * 256) * (tg_n[i] * bn);
     }
     if (kblocks > INT32_MAX / 2 || t128_m * kblocks > INT32_MAX / 2 || tn_total * kblocks > INT32_MAX / 2 ||
         (int64_t)D * (t128_m / 2) * tn_total > INT32_MAX / 2)
@@ -434,13 +435,14 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
     // constants: M = prod p_i, inv_i = (M / p_i)^{-1} mod p_i
     unsigned __int128 M = 1;
     for (int i = 0; i < D; ++i) M *= (unsigned)kCrtModuli[i];
-    int32_t inv[kCrtMaxModuli] = {0};
+    CrtScale inv;
+    std::memset(&inv, 0, sizeof(inv));
     for (int i = 0; i < D; ++i) {
         const int p = kCrtModuli[i];
         const int mi = (int)((M / (unsigned)p) % (unsigned)p);
         for (int v = 1; v < p; ++v)
             if ((mi * v) % p == 1) {
-                inv[i] = v;
+                inv.s[i] = v;
                 break;
             }
     }
@@ -475,7 +477,7 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
         const int64_t lt = ((L.m + 255) / 256) * 2;
         {
             ProfScope ps("crt_split_p", s);
-            if (launch_crt_split_rows(D, L.P, L.ldp, L.m, k, (int)lt, (int)kblocks, left_qc, (int8_t *)wsP, s) !=
+            if (launch_crt_split_rows(D, L.P, L.ldp, L.m, k, (int)lt, (int)kblocks, left_qc, inv, (int8_t *)wsP, s) !=
                 hipSuccess) {
                 release();
                 return HLB_EDEVICE;
@@ -494,17 +496,17 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
             a.tiles_m = (int)(lt / 2);
             a.group_m = 4;
             a.n_xcd = n_xcd;
-            for (int i = 0; i < D; ++i) a.inv[i] = inv[i];
             int32_t tb = 0;
             int64_t yoff = 0;
             for (size_t i = first; i < last; ++i) {
                 CrtSeg &sg = a.seg[a.nseg++];
                 sg.Y = (uint8_t *)wsY + yoff;
                 sg.n = rights[i].n;
-                sg.ldy = (rights[i].n + 15) / 16 * 16;
+                sg.nbc = tg_n[i] * bn / 32;
+                sg.plane = (lt / 2 * 256) * (tg_n[i] * bn);
                 sg.tile_begin = tb;
                 tb += (int32_t)tg_n[i];
-                yoff += (int64_t)D * L.m * sg.ldy;
+                yoff += (int64_t)D * sg.plane;
             }
             a.tiles_n = tb;
             tile_base += tb;
@@ -525,7 +527,8 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
                 c.C = L.C[i];
                 c.m = L.m;
                 c.n = sg.n;
-                c.ldy = sg.ldy;
+                c.nbc = sg.nbc;
+                c.plane = sg.plane;
                 c.ldc = L.ldc[i];
                 c.q = rights[i].q;
                 c.barrett = (uint64_t)((~(unsigned __int128)0 >> 64) / c.q);

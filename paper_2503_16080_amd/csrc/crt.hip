@@ -6,9 +6,10 @@
 //   1. split: the centred operands (plaintext as signed integers; residues x mod q taken in
 //      (-q/2, q/2]) become D planes of balanced residues modulo p_0 .. p_{D-1} <= 256, in the
 //      tile-major, swizzled layout of the digit split ([tile][k block][plane][128][64]);
-//   2. GEMM: one plain INT8 product per modulus and output tile (v_mfma_i32_32x32x32_i8,
-//      64 x 64 outputs per wave), |c| <= k 2^14 < 2^31; the epilogue writes the byte
-//      y_i = c * (M / p_i)^{-1} mod p_i;
+//      The left operand's residues are multiplied by (M / p_i)^{-1} mod p_i in the split;
+//   2. GEMM: one plain INT8 product per modulus and output tile (v_mfma_i32_32x32x32_i8),
+//      |c| <= k 2^14 < 2^31; by the factor above, the byte y_i = c mod p_i is already the
+//      CRT coefficient, and the epilogue writes it in the accumulator order (crt.hpp);
 //   3. combine: V = sum_i y_i (M / p_i) - t M with t = round(sum_i y_i / p_i) is the exact
 //      integer product as long as M > 2 |V|, and V mod q is formed from w_i = (M / p_i) mod q.
 // D moduli replace the DP * DX digit products of Strategy 1 (11 instead of 21 for a 20-bit
@@ -32,9 +33,10 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // ---------------------------------------------------------------------------------------
 constexpr int kCrtR = 128;  // rows (columns) per split tile
 
-template <int D>
-__device__ __forceinline__ void crt_store_chunk(const double (&v)[16], int8_t *blk, int r, int c) {
-    // blk: the [D][128][64] block of this (tile, k block); row r, logical chunk c
+template <int D, bool SCALED>
+__device__ __forceinline__ void crt_store_chunk(const double (&v)[16], int8_t *blk, int r, int c, const CrtScale scale) {
+    // blk: the [D][128][64] block of this (tile, k block); row r, logical chunk c.  With a
+    // scale, each residue x becomes the balanced residue of x * s_i (|x s_i| < 2^15, exact).
     int8_t *dst = blk + r * 64 + ((c ^ swz(r)) << 4);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -43,8 +45,11 @@ __device__ __forceinline__ void crt_store_chunk(const double (&v)[16], int8_t *b
         for (int q4 = 0; q4 < 4; ++q4) {
             uint32_t x = 0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                x |= ((uint32_t)balanced_residue(v[q4 * 4 + e], kCrtModuli[i]) & 0xffu) << (8 * e);
+            for (int e = 0; e < 4; ++e) {
+                int b = balanced_residue(v[q4 * 4 + e], kCrtModuli[i]);
+                if (SCALED) b = balanced_residue((double)(b * scale.s[i]), kCrtModuli[i]);
+                x |= ((uint32_t)b & 0xffu) << (8 * e);
+            }
             w[q4] = x;
         }
         *(uint4 *)(dst + i * kCrtR * 64) = uint4{w[0], w[1], w[2], w[3]};
@@ -59,7 +64,8 @@ __device__ __forceinline__ double crt_centred(uint64_t x, uint64_t qc) {
 // grid: (tiles * kblocks) workgroups of 512 threads = 128 rows x 4 chunks
 template <int D>
 __global__ __launch_bounds__(512) void crt_split_rows(const int64_t *__restrict__ P, int64_t ldp, int64_t m,
-                                                      int64_t k, int kblocks, uint64_t qc, int8_t *__restrict__ out) {
+                                                      int64_t k, int kblocks, uint64_t qc, const CrtScale scale,
+                                                      int8_t *__restrict__ out) {
     const int tile = blockIdx.x / kblocks, kb = blockIdx.x % kblocks;
     const int r = threadIdx.x >> 2, c = threadIdx.x & 3;
     const int64_t row = (int64_t)tile * kCrtR + r;
@@ -73,7 +79,7 @@ __global__ __launch_bounds__(512) void crt_split_rows(const int64_t *__restrict_
     double v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = (row < m && k0 + e < k) ? crt_centred(x[e], qc) : 0.0;
-    crt_store_chunk<D>(v, out + ((int64_t)tile * kblocks + kb) * (D * kCrtR * kBK8), r, c);
+    crt_store_chunk<D, true>(v, out + ((int64_t)tile * kblocks + kb) * (D * kCrtR * kBK8), r, c, scale);
 }
 
 template <int D>
@@ -92,7 +98,7 @@ __global__ __launch_bounds__(512) void crt_split_cols(const uint64_t *__restrict
     double v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = (col < n && k0 + e < k) ? crt_centred(x[e], qc) : 0.0;
-    crt_store_chunk<D>(v, out + ((int64_t)tile * kblocks + kb) * (D * kCrtR * kBK8), r, c);
+    crt_store_chunk<D, false>(v, out + ((int64_t)tile * kblocks + kb) * (D * kCrtR * kBK8), r, c, CrtScale{});
 }
 
 // ---------------------------------------------------------------------------------------
@@ -121,17 +127,17 @@ struct CrtTile {
 using CrtNarrow = CrtTile<2, 2, 4, 2>;
 using CrtWide = CrtTile<2, 4, 4, 2>;
 
-__device__ __forceinline__ uint8_t crt_y(int c, int p, int inv) {
-    // (c mod p) * inv mod p, in [0, p); c and the products are exact in double
-    const double pd = (double)p, pinv = 1.0 / pd;
-    double r = __builtin_fma(-__builtin_floor((double)c * pinv), pd, (double)c);
-    r = r < 0.0 ? r + pd : r;
-    r = r >= pd ? r - pd : r;
-    double y = r * (double)inv;
-    y = __builtin_fma(-__builtin_floor(y * pinv), pd, y);
-    y = y < 0.0 ? y + pd : y;
-    y = y >= pd ? y - pd : y;
-    return (uint8_t)(int)y;
+// c mod p in [0, p) for any int32 c and p <= 256: with c = h 2^16 + l (h signed, 0 <= l <
+// 2^16), u = h (2^16 mod p) + l satisfies |u| < 2^24, so u and the quotient estimate
+// floor(u / p) are exact in single precision up to one unit, which one correction each way
+// removes.  Integer products stay below 2^24 (24-bit multiply-adds).
+__device__ __forceinline__ uint32_t crt_y(int c, int p, int c16, float pinv) {
+    const int u = (c >> 16) * c16 + (c & 0xffff);
+    const int t = (int)__builtin_floorf((float)u * pinv);
+    int r = u - t * p;
+    r = r < 0 ? r + p : r;
+    r = r >= p ? r - p : r;
+    return (uint32_t)r;
 }
 
 template <class T>
@@ -250,22 +256,23 @@ __global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_kernel(const CrtGemmAr
         }
     }
 
+    // epilogue: one 16-byte store per 32 x 32 block and lane (the plane covers whole tiles)
     const int p = kCrtModuli[mi];
-    const int inv = args.inv[mi];
-    const int64_t m0 = (int64_t)rb * kCrtBM + wm * 32 * MB;
-    const int64_t n0 = (int64_t)(cb - sg.tile_begin) * T::BN + wn * 32 * NB;
-    uint8_t *Y = sg.Y + (int64_t)mi * args.m * sg.ldy;
+    const int c16 = (1 << 16) % p;
+    const float pinv = 1.0f / (float)p;
+    const int64_t br0 = (int64_t)rb * (kCrtBM / 32) + wm * MB;
+    const int64_t bc0 = (int64_t)(cb - sg.tile_begin) * (T::BN / 32) + wn * NB;
+    uint8_t *Y = sg.Y + (int64_t)mi * sg.plane;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
+        for (int nb = 0; nb < NB; ++nb) {
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                // 32x32 accumulator layout: column = lane % 32, row = 8 (r / 4) + 4 (lane / 32) + r % 4
-                const int64_t row = m0 + mb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int64_t col = n0 + nb * 32 + (lane & 31);
-                if (row < args.m && col < sg.n) Y[row * sg.ldy + col] = crt_y(acc[mb][nb][r], p, inv);
-            }
+            for (int r = 0; r < 16; ++r) w[r >> 2] |= crt_y(acc[mb][nb][r], p, c16, pinv) << (8 * (r & 3));
+            const int64_t blk = (br0 + mb) * sg.nbc + bc0 + nb;
+            *(uint4 *)(Y + (blk * 64 + lane) * 16) = uint4{w[0], w[1], w[2], w[3]};
+        }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -279,39 +286,48 @@ __device__ __forceinline__ uint64_t reduce_u64(uint64_t x, uint64_t q, uint64_t 
     return r >= q ? r - q : r;
 }
 
-// Thread: 4 consecutive columns of one row.  The D planes are read as one dword each (the
-// plane rows are padded to 16 bytes), sum_i y_i w_i < 16 * 2^8 * 2^52 accumulates without
+// Thread: one lane's 16 entries of one 32 x 32 block (16 bytes of every plane, read as one
+// 16-byte load each); consecutive threads are consecutive lanes, so each row of a block is
+// written as 256 contiguous bytes.  sum_i y_i w_i < 16 * 2^8 * 2^52 accumulates without
 // reduction, and the rounding t = round(sum_i y_i / p_i) needs only single precision: the
 // fraction lies within 1/4 of an integer, far beyond its rounding error.
 __global__ __launch_bounds__(kThreads) void crt_combine_kernel(const CrtCombineArgs a) {
-    const int64_t plane = a.m * a.ldy;
-    for (int64_t row = blockIdx.y; row < a.m; row += gridDim.y) {
-        for (int64_t c4 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; c4 < a.n;
-             c4 += (int64_t)gridDim.x * blockDim.x * 4) {
-            const uint8_t *y = a.Y + row * a.ldy + c4;
-            uint64_t s[4] = {0, 0, 0, 0};
-            float f[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-            for (int i = 0; i < a.D; ++i) {
-                const uint32_t v = *(const uint32_t *)(y + (int64_t)i * plane);
-                const uint64_t w = a.w[i];
-                const float pi = a.pinv[i];
+    const int64_t nbr = (a.m + 31) >> 5, nbc_valid = (a.n + 31) >> 5;
+    const int64_t total = nbr * nbc_valid * 64;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(g & 63);
+        const int64_t b = g >> 6, br = b / nbc_valid, bc = b - br * nbc_valid;
+        const uint8_t *y = a.Y + ((br * a.nbc + bc) * 64 + lane) * 16;
+        uint64_t s[16];
+        float f[16];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const uint32_t b = (v >> (8 * e)) & 0xffu;
-                    s[e] += (uint64_t)b * w;
-                    f[e] = __builtin_fmaf((float)b, pi, f[e]);
-                }
-            }
-            uint64_t *out = a.C + row * a.ldc + c4;
+        for (int e = 0; e < 16; ++e) {
+            s[e] = 0;
+            f[e] = 0.f;
+        }
+#pragma unroll 2
+        for (int i = 0; i < a.D; ++i) {
+            const uint4 v = *(const uint4 *)(y + (int64_t)i * a.plane);
+            const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+            const uint64_t w = a.w[i];
+            const float pi = a.pinv[i];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                if (c4 + e >= a.n) break;
-                const uint64_t t = (uint64_t)__builtin_floorf(f[e] + 0.5f);
-                const uint64_t sr = reduce_u64(s[e], a.q, a.barrett);
-                const uint64_t tm = reduce_u64(t * a.Mq, a.q, a.barrett);
-                out[e] = sr >= tm ? sr - tm : sr + a.q - tm;
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t byte = (vw[e >> 2] >> (8 * (e & 3))) & 0xffu;
+                s[e] += (uint64_t)byte * w;
+                f[e] = __builtin_fmaf((float)byte, pi, f[e]);
             }
+        }
+        const int64_t col = bc * 32 + (lane & 31);
+        if (col >= a.n) continue;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int64_t row = br * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+            if (row >= a.m) continue;
+            const uint64_t t = (uint64_t)__builtin_floorf(f[e] + 0.5f);
+            const uint64_t sr = reduce_u64(s[e], a.q, a.barrett);
+            const uint64_t tm = reduce_u64(t * a.Mq, a.q, a.barrett);
+            a.C[row * a.ldc + col] = sr >= tm ? sr - tm : sr + a.q - tm;
         }
     }
 }
@@ -330,11 +346,11 @@ int crt_round_d(int D) {
 #define HLB_CRT_D(X) X(8) X(10) X(11) X(12) X(14) X(16)
 
 hipError_t launch_crt_split_rows(int D, const int64_t *P, int64_t ldp, int64_t m, int64_t k, int tiles, int kblocks,
-                                 uint64_t qc, int8_t *out, hipStream_t s) {
+                                 uint64_t qc, const CrtScale &scale, int8_t *out, hipStream_t s) {
     if (tiles <= 0 || kblocks <= 0) return hipSuccess;
     const dim3 g(tiles * kblocks), b(512);
 #define HLB_CASE(DD) \
-    if (D == DD) { hipLaunchKernelGGL(crt_split_rows<DD>, g, b, 0, s, P, ldp, m, k, kblocks, qc, out); return hipGetLastError(); }
+    if (D == DD) { hipLaunchKernelGGL(crt_split_rows<DD>, g, b, 0, s, P, ldp, m, k, kblocks, qc, scale, out); return hipGetLastError(); }
     HLB_CRT_D(HLB_CASE)
 #undef HLB_CASE
     return hipErrorInvalidValue;
@@ -368,10 +384,10 @@ hipError_t launch_crt_gemm(int variant, const CrtGemmArgs &a, hipStream_t s) {
 
 hipError_t launch_crt_combine(const CrtCombineArgs &a, hipStream_t s) {
     if (a.m <= 0 || a.n <= 0) return hipSuccess;
-    int64_t gx = (a.n + kThreads * 4 - 1) / (kThreads * 4);
-    gx = gx > 1024 ? 1024 : gx;
-    const int64_t gy = a.m > 65535 ? 65535 : a.m;
-    hipLaunchKernelGGL(crt_combine_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, a);
+    const int64_t threads = ((a.m + 31) / 32) * ((a.n + 31) / 32) * 64;
+    int64_t g = (threads + kThreads - 1) / kThreads;
+    g = g > (1 << 20) ? (1 << 20) : g;
+    hipLaunchKernelGGL(crt_combine_kernel, dim3((unsigned)g), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 

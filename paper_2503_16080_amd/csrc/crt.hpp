@@ -31,38 +31,50 @@ __device__ __forceinline__ int balanced_residue(double v, int p) {
     return ri >= (p + 1) / 2 ? ri - p : ri;
 }
 
-// GEMM of one modulus: C_i = P_i X_i (int32, exact), then y = C_i * inv_i mod p_i as a byte.
+// Product planes.  The GEMM of modulus i writes y_i = C_i mod p_i as one byte per entry (the
+// left operand's residues carry the factor (M / p_i)^{-1}, so y_i is already the CRT
+// coefficient).  A plane covers the output padded to whole GEMM tiles and is stored in the
+// accumulator order of v_mfma_i32_32x32x32_i8: 32 x 32 blocks, row-major over the padded grid,
+// each block as 64 lanes x 16 bytes, where lane l, byte r holds row 8 (r / 4) + 4 (l / 32) +
+// r % 4 and column l % 32 of the block.  Each lane thus stores its 16 results as one
+// contiguous 16-byte write.
 struct CrtSeg {
-    uint8_t *Y;          // [D][m][ldy] bytes of this output matrix
-    int64_t n, ldy;      // ldy: n rounded up to a multiple of 16
+    uint8_t *Y;          // [D][plane] bytes of this output matrix
+    int64_t n;           // valid columns
+    int64_t nbc;         // 32-column blocks per padded row
+    int64_t plane;       // bytes per modulus: padded rows x padded columns
     int32_t tile_begin;  // first global GEMM column tile
     int32_t pad;
 };
 
 struct CrtGemmArgs {
-    const int8_t *Pd;    // plaintext planes: [128-row tile][k block][D][128][64]
-    const int8_t *Xd;    // residue planes:   [128-col tile][k block][D][128][64]
+    const int8_t *Pd;    // left operand planes: [128-row tile][k block][D][128][64]
+    const int8_t *Xd;    // right operand planes: [128-col tile][k block][D][128][64]
     int64_t m;
     int32_t kblocks, D;
     int32_t tiles_m;     // 256-row tiles
     int32_t tiles_n;     // GEMM column tiles (128 or 256 wide) over all segments
     int32_t group_m, n_xcd, nseg, pad;
-    int32_t inv[kCrtMaxModuli];  // (M / p_i)^{-1} mod p_i
     CrtSeg seg[kMaxSegs];
 };
 
 // Recombination of one output matrix: V = sum_i y_i (M / p_i) - t M with t the nearest
 // integer to sum_i y_i / p_i, reduced modulo q through w_i = (M / p_i) mod q and M mod q.
 struct CrtCombineArgs {
-    const uint8_t *Y;    // [D][m][ldy]
+    const uint8_t *Y;    // [D][plane], layout of CrtSeg
     uint64_t *C;
-    int64_t m, n, ldy, ldc;
+    int64_t m, n, nbc, plane, ldc;
     uint64_t q;
     uint64_t barrett;    // floor(2^64 / q)
     uint64_t Mq;         // M mod q
     uint64_t w[kCrtMaxModuli];
     float pinv[kCrtMaxModuli];  // 1 / p_i
     int32_t D, pad;
+};
+
+// Factors applied to the left operand's residues in the split: (M / p_i)^{-1} mod p_i.
+struct CrtScale {
+    int32_t s[kCrtMaxModuli];
 };
 
 }  // namespace hlb

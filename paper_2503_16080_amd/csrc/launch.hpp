@@ -49,11 +49,13 @@ hipError_t launch_prep_x_planes(int nx, bool trunc, const uint64_t *X, int64_t l
 hipError_t launch_gemm_f64_planes(int nx, bool trunc, const GemmArgs &a, hipStream_t s);
 
 // Multimodular (CRT) INT8 form: residue splits (qc = 0: signed values; else residues mod qc
-// taken centred), one INT8 GEMM per modulus, recombination.  D must be crt_supported_d.
+// taken centred; the left operand's residues are multiplied by scale.s[i] mod p_i), one INT8
+// GEMM per modulus, recombination.  D must be crt_supported_d.
 bool crt_supported_d(int D);
 int crt_round_d(int D);  // smallest supported D >= D, or 0
+struct CrtScale;
 hipError_t launch_crt_split_rows(int D, const int64_t *P, int64_t ldp, int64_t m, int64_t k, int tiles, int kblocks,
-                                 uint64_t qc, int8_t *out, hipStream_t s);
+                                 uint64_t qc, const CrtScale &scale, int8_t *out, hipStream_t s);
 hipError_t launch_crt_split_cols(int D, const uint64_t *X, int64_t ldx, int64_t k, int64_t n, int tiles, int kblocks,
                                  uint64_t qc, int8_t *out, hipStream_t s);
 struct CrtGemmArgs;
