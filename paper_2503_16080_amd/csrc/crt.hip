@@ -33,32 +33,38 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // ---------------------------------------------------------------------------------------
 constexpr int kCrtR = 128;  // rows (columns) per split tile
 
-template <int D, bool SCALED>
-__device__ __forceinline__ void crt_store_chunk(const double (&v)[16], int8_t *blk, int r, int c, const CrtScale scale) {
-    // blk: the [D][128][64] block of this (tile, k block); row r, logical chunk c.  With a
-    // scale, each residue x becomes the balanced residue of x * s_i (|x s_i| < 2^15, exact).
-    int8_t *dst = blk + r * 64 + ((c ^ swz(r)) << 4);
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
+template <int I, int D, bool SCALED>
+__device__ __forceinline__ void crt_store_planes(const CrtPieces (&x)[16], int8_t *dst, const CrtScale &scale) {
+    if constexpr (I < D) {
         uint32_t w[4];
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
-            uint32_t x = 0;
+            uint32_t v = 0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                int b = balanced_residue(v[q4 * 4 + e], kCrtModuli[i]);
-                if (SCALED) b = balanced_residue((double)(b * scale.s[i]), kCrtModuli[i]);
-                x |= ((uint32_t)b & 0xffu) << (8 * e);
+                int b = crt_residue<I>(x[q4 * 4 + e]);
+                if constexpr (SCALED) b = crt_balanced(__mul24(b, scale.s[I]), kCrtModuli[I], 1.0f / (float)kCrtModuli[I]);
+                v |= ((uint32_t)b & 0xffu) << (8 * e);
             }
-            w[q4] = x;
+            w[q4] = v;
         }
-        *(uint4 *)(dst + i * kCrtR * 64) = uint4{w[0], w[1], w[2], w[3]};
+        *(uint4 *)(dst + I * kCrtR * 64) = uint4{w[0], w[1], w[2], w[3]};
+        crt_store_planes<I + 1, D, SCALED>(x, dst, scale);
     }
 }
 
-__device__ __forceinline__ double crt_centred(uint64_t x, uint64_t qc) {
-    const int64_t s = (qc != 0 && 2 * x > qc) ? (int64_t)x - (int64_t)qc : (int64_t)x;
-    return (double)s;
+// blk: the [D][128][64] block of this (tile, k block); row r, logical chunk c.  With SCALED,
+// each residue b becomes the balanced residue of b * s_i (|b s_i| < 2^15).
+template <int D, bool SCALED>
+__device__ __forceinline__ void crt_store_chunk(const int64_t (&v)[16], int8_t *blk, int r, int c, const CrtScale scale) {
+    CrtPieces x[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = crt_pieces(v[e]);
+    crt_store_planes<0, D, SCALED>(x, blk + r * 64 + ((c ^ swz(r)) << 4), scale);
+}
+
+__device__ __forceinline__ int64_t crt_centred(uint64_t x, uint64_t qc) {
+    return (qc != 0 && 2 * x > qc) ? (int64_t)x - (int64_t)qc : (int64_t)x;
 }
 
 // grid: (tiles * kblocks) workgroups of 512 threads = 128 rows x 4 chunks
@@ -76,9 +82,9 @@ __global__ __launch_bounds__(512) void crt_split_rows(const int64_t *__restrict_
     for (int e = 0; e < 16; ++e) x[e] = (uint64_t)P[rc * ldp + (k0 + e < k ? k0 + e : k - 1)];
 #pragma unroll
     for (int e = 0; e < 16; ++e) asm volatile("" : "+v"(x[e]));  // all loads issued before the masks
-    double v[16];
+    int64_t v[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = (row < m && k0 + e < k) ? crt_centred(x[e], qc) : 0.0;
+    for (int e = 0; e < 16; ++e) v[e] = (row < m && k0 + e < k) ? crt_centred(x[e], qc) : 0;
     crt_store_chunk<D, true>(v, out + ((int64_t)tile * kblocks + kb) * (D * kCrtR * kBK8), r, c, scale);
 }
 
@@ -95,9 +101,9 @@ __global__ __launch_bounds__(512) void crt_split_cols(const uint64_t *__restrict
     for (int e = 0; e < 16; ++e) x[e] = X[(k0 + e < k ? k0 + e : k - 1) * ldx + cc];
 #pragma unroll
     for (int e = 0; e < 16; ++e) asm volatile("" : "+v"(x[e]));
-    double v[16];
+    int64_t v[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = (col < n && k0 + e < k) ? crt_centred(x[e], qc) : 0.0;
+    for (int e = 0; e < 16; ++e) v[e] = (col < n && k0 + e < k) ? crt_centred(x[e], qc) : 0;
     crt_store_chunk<D, false>(v, out + ((int64_t)tile * kblocks + kb) * (D * kCrtR * kBK8), r, c, CrtScale{});
 }
 
@@ -288,21 +294,25 @@ __device__ __forceinline__ uint64_t reduce_u64(uint64_t x, uint64_t q, uint64_t 
 
 // Thread: one lane's 16 entries of one 32 x 32 block (16 bytes of every plane, read as one
 // 16-byte load each); consecutive threads are consecutive lanes, so each row of a block is
-// written as 256 contiguous bytes.  sum_i y_i w_i < 16 * 2^8 * 2^52 accumulates without
-// reduction, and the rounding t = round(sum_i y_i / p_i) needs only single precision: the
-// fraction lies within 1/4 of an integer, far beyond its rounding error.
+// written as 256 contiguous bytes.  S = sum_i y_i w_i < 16 * 2^8 * 2^52 is accumulated in
+// three 20-bit limbs of w_i (each limb sum stays below 2^32, 24-bit multiply-adds), and the
+// rounding t = round(sum_i y_i / p_i) needs only single precision: the fraction lies within
+// 1/4 of an integer, far beyond its rounding error.  (t M) mod q comes from a table in LDS.
 __global__ __launch_bounds__(kThreads) void crt_combine_kernel(const CrtCombineArgs a) {
+    __shared__ uint64_t tmq[kCrtMaxModuli + 1];
+    if (threadIdx.x <= (unsigned)a.D) tmq[threadIdx.x] = reduce_u64((uint64_t)threadIdx.x * a.Mq, a.q, a.barrett);
+    __syncthreads();
     const int64_t nbr = (a.m + 31) >> 5, nbc_valid = (a.n + 31) >> 5;
     const int64_t total = nbr * nbc_valid * 64;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
         const int lane = (int)(g & 63);
         const int64_t b = g >> 6, br = b / nbc_valid, bc = b - br * nbc_valid;
         const uint8_t *y = a.Y + ((br * a.nbc + bc) * 64 + lane) * 16;
-        uint64_t s[16];
+        uint32_t s0[16], s1[16], s2[16];
         float f[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            s[e] = 0;
+            s0[e] = s1[e] = s2[e] = 0u;
             f[e] = 0.f;
         }
 #pragma unroll 2
@@ -310,11 +320,14 @@ __global__ __launch_bounds__(kThreads) void crt_combine_kernel(const CrtCombineA
             const uint4 v = *(const uint4 *)(y + (int64_t)i * a.plane);
             const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
             const uint64_t w = a.w[i];
+            const uint32_t w0 = (uint32_t)w & 0xfffffu, w1 = (uint32_t)(w >> 20) & 0xfffffu, w2 = (uint32_t)(w >> 40);
             const float pi = a.pinv[i];
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const uint32_t byte = (vw[e >> 2] >> (8 * (e & 3))) & 0xffu;
-                s[e] += (uint64_t)byte * w;
+                s0[e] += __umul24(byte, w0);
+                s1[e] += __umul24(byte, w1);
+                s2[e] += __umul24(byte, w2);
                 f[e] = __builtin_fmaf((float)byte, pi, f[e]);
             }
         }
@@ -324,9 +337,9 @@ __global__ __launch_bounds__(kThreads) void crt_combine_kernel(const CrtCombineA
         for (int e = 0; e < 16; ++e) {
             const int64_t row = br * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
             if (row >= a.m) continue;
-            const uint64_t t = (uint64_t)__builtin_floorf(f[e] + 0.5f);
-            const uint64_t sr = reduce_u64(s[e], a.q, a.barrett);
-            const uint64_t tm = reduce_u64(t * a.Mq, a.q, a.barrett);
+            const uint64_t sum = ((uint64_t)s2[e] << 40) + ((uint64_t)s1[e] << 20) + s0[e];
+            const uint64_t sr = reduce_u64(sum, a.q, a.barrett);
+            const uint64_t tm = tmq[(int)__builtin_floorf(f[e] + 0.5f)];
             a.C[row * a.ldc + col] = sr >= tm ? sr - tm : sr + a.q - tm;
         }
     }

@@ -18,17 +18,37 @@ constexpr int kCrtMaxModuli = 16;
 constexpr int kCrtModuli[kCrtMaxModuli] = {256, 255, 253, 251, 247, 241, 239, 233,
                                            229, 227, 223, 211, 199, 197, 193, 191};
 
-// Balanced residue of an integer-valued double |v| < 2^52 modulo p <= 256, in
-// [-(p/2), (p-1)/2]: the quotient estimate floor(v / p) is off by at most one, and the fused
-// multiply-add forming the remainder is exact.
-__device__ __forceinline__ int balanced_residue(double v, int p) {
-    const double pd = (double)p;
-    const double t = __builtin_floor(v * (1.0 / pd));
-    double r = __builtin_fma(-t, pd, v);
-    r = r < 0.0 ? r + pd : r;
-    r = r >= pd ? r - pd : r;
-    const int ri = (int)r;
-    return ri >= (p + 1) / 2 ? ri - p : ri;
+constexpr int crt_pow2_mod(int e, int p) {
+    int r = 1 % p;
+    for (int i = 0; i < e; ++i) r = (2 * r) % p;
+    return r;
+}
+
+// A signed integer |s| < 2^52 as s = a 2^32 + b 2^16 + c with |a| <= 2^20, 0 <= b, c < 2^16.
+struct CrtPieces {
+    int a, b, c;
+};
+__device__ __forceinline__ CrtPieces crt_pieces(int64_t s) {
+    return {(int)(s >> 32), (int)(((uint64_t)s >> 16) & 0xffffu), (int)((uint64_t)s & 0xffffu)};
+}
+
+// Balanced residue of an integer |u| < 2^29 modulo p <= 256, in [-(p/2), (p-1)/2]: the
+// nearest-integer quotient estimate from single precision is off by at most one (|u| / p
+// carries an error below 0.3), and one correction each way removes that.
+__device__ __forceinline__ int crt_balanced(int u, int p, float pinv) {
+    const int t = (int)__builtin_floorf(__builtin_fmaf((float)u, pinv, 0.5f));
+    int r = u - __mul24(t, p);
+    r = r > (p - 1) / 2 ? r - p : r;
+    return r < -(p / 2) ? r + p : r;
+}
+
+// Balanced residue of the pieces modulo the i-th modulus: a (2^32 mod p) + b (2^16 mod p) + c
+// is congruent to s and below 2^28.1 in magnitude.
+template <int I>
+__device__ __forceinline__ int crt_residue(const CrtPieces &x) {
+    constexpr int p = kCrtModuli[I];
+    constexpr int e32 = crt_pow2_mod(32, p), e16 = crt_pow2_mod(16, p);
+    return crt_balanced(__mul24(x.a, e32) + __mul24(x.b, e16) + x.c, p, 1.0f / (float)p);
 }
 
 // Product planes.  The GEMM of modulus i writes y_i = C_i mod p_i as one byte per entry (the
