@@ -66,10 +66,11 @@ _CSRC = os.path.join(ROOT, "paper_2503_16080_amd", "csrc")
 # SHA-256 they are valid for, and the kernel-name substring that selects their dispatches.
 TRAFFIC = {
     "crt_gemm": {"file": os.path.join(ROOT, "profiles", "crt_gemm_traffic.json"),
-                 "sources": [os.path.join(_CSRC, f) for f in ("crt.hip", "crt.hpp", "common.hpp")],
+                 # api.cpp decides how the work is cut into launches (per-dispatch counters)
+                 "sources": [os.path.join(_CSRC, f) for f in ("crt.hip", "crt.hpp", "common.hpp", "api.cpp")],
                  "match": "crt_gemm_kernel"},
     "gemm_i8": {"file": os.path.join(ROOT, "profiles", "gemm_i8_traffic.json"),
-                "sources": [os.path.join(_CSRC, f) for f in ("gemm_i8.hip", "i8_tile.hpp", "common.hpp")],
+                "sources": [os.path.join(_CSRC, f) for f in ("gemm_i8.hip", "i8_tile.hpp", "common.hpp", "api.cpp")],
                 "match": "gemm_i8_kernel"},
 }
 
@@ -367,12 +368,16 @@ def main():
         hlb.profile_reset()
         return s, {n: (c, t / max(c, 1)) for n, (c, t) in prof.items()}
 
-    def roofline(kernel, launches, ms, ops):
+    def roofline(kernel, launches, ms, ops_per_step, steps):
+        # a step may cut the GEMM into several launches (one per right operand): the
+        # algorithmic work of one launch is the step's work over its launches
+        per_step = launches / steps
+        ops = ops_per_step / per_step
         tops = ops / (ms * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": tops, "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
                 "frac": tops / INT8_PEAK_TOPS, "traffic": measured_traffic(kernel, d, L),
                 "kernel": TRAFFIC[kernel]["match"], "avg_launch_ms": ms, "launches": launches,
-                "ops_per_launch": ops, "op": "int8 MAC x 2"}
+                "launches_per_step": per_step, "ops_per_launch": ops, "op": "int8 MAC x 2"}
 
     # Headline: the multimodular INT8 form (Strategy 3; D int8 products per mod-q MAC)
     cplan = hlb.plan(1, d, max(w.primes), w.p_absmax, "int8_crt")
@@ -392,7 +397,7 @@ def main():
                                f"(multimodular: {cplan['p_limbs']} int8 products per mod-q MAC)",
                    "m": d, "k": d, "n": d, "primes": L, "prime_bits": args.bits, "form": "int8_crt",
                    "moduli": cplan["p_limbs"]},
-        "roofline": roofline("crt_gemm", kc["crt_gemm"][0], kc["crt_gemm"][1], c_ops),
+        "roofline": roofline("crt_gemm", kc["crt_gemm"][0], kc["crt_gemm"][1], c_ops, args.steps),
         "kernels_ms": {n: v[1] for n, v in kc.items()},
     }
 
@@ -404,7 +409,7 @@ def main():
         out["int8_digit_form"] = {
             "value": macs / s_dig, "unit": "mod-q MAC/s", "ms_per_step": s_dig * 1e3,
             "digits": [dplan["p_limbs"], dplan["x_limbs"]],
-            "roofline": roofline("gemm_i8", kd["gemm_i8"][0], kd["gemm_i8"][1], d_ops),
+            "roofline": roofline("gemm_i8", kd["gemm_i8"][0], kd["gemm_i8"][1], d_ops, args.steps),
             "kernels_ms": {n: v[1] for n, v in kd.items()}}
 
     if not args.no_fp64:

@@ -460,90 +460,111 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
         release();
         return st;
     }
-    int64_t t0 = 0;
-    for (size_t i = 0; i < rights.size(); ++i) {
-        ProfScope ps("crt_split_x", s);
-        if (launch_crt_split_cols(D, rights[i].X, rights[i].ldx, k, rights[i].n, (int)t128_n[i], (int)kblocks,
-                                  rights[i].q, (int8_t *)wsX + t0 * kblocks * sub, s) != hipSuccess) {
+    // offsets of each right operand's split tiles (128 wide) and product planes
+    std::vector<int64_t> x_tile0(rights.size()), y_off(rights.size());
+    {
+        int64_t t0 = 0, y0 = 0;
+        for (size_t i = 0; i < rights.size(); ++i) {
+            x_tile0[i] = t0;
+            y_off[i] = y0;
+            t0 += t128_n[i];
+            y0 += (int64_t)D * (t128_m / 2 * 256) * (tg_n[i] * bn);
+        }
+    }
+    auto split_x = [&](size_t i, hipStream_t st) -> bool {
+        ProfScope ps("crt_split_x", st);
+        return launch_crt_split_cols(D, rights[i].X, rights[i].ldx, k, rights[i].n, (int)t128_n[i], (int)kblocks,
+                                     rights[i].q, (int8_t *)wsX + x_tile0[i] * kblocks * sub, st) == hipSuccess;
+    };
+    // a left operand holding residues is centred modulo the (shared) modulus of the products
+    const uint64_t left_qc = pl.kind == 0 ? rights[0].q : 0;
+    auto split_p = [&](const LeftSpec &L, hipStream_t st) -> bool {
+        ProfScope ps("crt_split_p", st);
+        const int64_t lt = ((L.m + 255) / 256) * 2;
+        return launch_crt_split_rows(D, L.P, L.ldp, L.m, k, (int)lt, (int)kblocks, left_qc, inv, (int8_t *)wsP, st) ==
+               hipSuccess;
+    };
+    // product planes of right operand i for left operand L
+    auto segment = [&](const LeftSpec &L, size_t i) {
+        CrtSeg sg;
+        std::memset(&sg, 0, sizeof(sg));
+        const int64_t lt = ((L.m + 255) / 256) * 2;
+        sg.Y = (uint8_t *)wsY + y_off[i];
+        sg.n = rights[i].n;
+        sg.nbc = tg_n[i] * bn / 32;
+        sg.plane = (lt / 2 * 256) * (tg_n[i] * bn);
+        return sg;
+    };
+    // one GEMM launch for right operands [first, last), all D moduli
+    auto gemm = [&](const LeftSpec &L, size_t first, size_t last, hipStream_t st) -> bool {
+        CrtGemmArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.Pd = (const int8_t *)wsP;
+        a.Xd = (const int8_t *)wsX + x_tile0[first] * kblocks * sub;
+        a.m = L.m;
+        a.kblocks = (int)kblocks;
+        a.D = D;
+        a.tiles_m = (int)((L.m + 255) / 256);
+        a.group_m = 4;
+        a.n_xcd = n_xcd;
+        int32_t tb = 0;
+        for (size_t i = first; i < last; ++i) {
+            CrtSeg &sg = a.seg[a.nseg++];
+            sg = segment(L, i);
+            sg.tile_begin = tb;
+            tb += (int32_t)tg_n[i];
+        }
+        a.tiles_n = tb;
+        if (tb == 0) return true;
+        ProfScope ps("crt_gemm", st);
+        return launch_crt_gemm(wide, a, st) == hipSuccess;
+    };
+    auto combine = [&](const LeftSpec &L, size_t i, hipStream_t st) -> bool {
+        if (rights[i].n == 0) return true;
+        const CrtSeg sg = segment(L, i);
+        CrtCombineArgs c;
+        std::memset(&c, 0, sizeof(c));
+        c.Y = sg.Y;
+        c.C = L.C[i];
+        c.m = L.m;
+        c.n = sg.n;
+        c.nbc = sg.nbc;
+        c.plane = sg.plane;
+        c.ldc = L.ldc[i];
+        c.q = rights[i].q;
+        c.barrett = (uint64_t)((~(unsigned __int128)0 >> 64) / c.q);
+        c.Mq = (uint64_t)(M % c.q);
+        c.D = D;
+        for (int j = 0; j < D; ++j) {
+            c.w[j] = (uint64_t)((M / (unsigned)kCrtModuli[j]) % c.q);
+            c.pinv[j] = 1.0f / (float)kCrtModuli[j];
+        }
+        ProfScope ps("crt_combine", st);
+        return launch_crt_combine(c, st) == hipSuccess;
+    };
+
+    for (size_t i = 0; i < rights.size(); ++i)
+        if (!split_x(i, s)) {
             release();
             return HLB_EDEVICE;
         }
-        t0 += t128_n[i];
-    }
-    // a left operand holding residues is centred modulo the (shared) modulus of the products
-    const uint64_t left_qc = pl.kind == 0 ? rights[0].q : 0;
     for (const LeftSpec &L : lefts) {
         if (L.m == 0) continue;
-        const int64_t lt = ((L.m + 255) / 256) * 2;
-        {
-            ProfScope ps("crt_split_p", s);
-            if (launch_crt_split_rows(D, L.P, L.ldp, L.m, k, (int)lt, (int)kblocks, left_qc, inv, (int8_t *)wsP, s) !=
-                hipSuccess) {
+        if (!split_p(L, s)) {
+            release();
+            return HLB_EDEVICE;
+        }
+        for (size_t first = 0; first < rights.size(); first += kMaxSegs) {
+            const size_t last = std::min(rights.size(), first + kMaxSegs);
+            if (!gemm(L, first, last, s)) {
                 release();
                 return HLB_EDEVICE;
             }
-        }
-        int64_t tile_base = 0;
-        for (size_t first = 0; first < rights.size(); first += kMaxSegs) {
-            const size_t last = std::min(rights.size(), first + kMaxSegs);
-            CrtGemmArgs a;
-            std::memset(&a, 0, sizeof(a));
-            a.Pd = (const int8_t *)wsP;
-            a.Xd = (const int8_t *)wsX + tile_base * xsub * kblocks * sub;
-            a.m = L.m;
-            a.kblocks = (int)kblocks;
-            a.D = D;
-            a.tiles_m = (int)(lt / 2);
-            a.group_m = 4;
-            a.n_xcd = n_xcd;
-            int32_t tb = 0;
-            int64_t yoff = 0;
-            for (size_t i = first; i < last; ++i) {
-                CrtSeg &sg = a.seg[a.nseg++];
-                sg.Y = (uint8_t *)wsY + yoff;
-                sg.n = rights[i].n;
-                sg.nbc = tg_n[i] * bn / 32;
-                sg.plane = (lt / 2 * 256) * (tg_n[i] * bn);
-                sg.tile_begin = tb;
-                tb += (int32_t)tg_n[i];
-                yoff += (int64_t)D * sg.plane;
-            }
-            a.tiles_n = tb;
-            tile_base += tb;
-            if (tb == 0) continue;
-            {
-                ProfScope ps("crt_gemm", s);
-                if (launch_crt_gemm(wide, a, s) != hipSuccess) {
+            for (size_t i = first; i < last; ++i)
+                if (!combine(L, i, s)) {
                     release();
                     return HLB_EDEVICE;
                 }
-            }
-            for (size_t i = first; i < last; ++i) {
-                const CrtSeg &sg = a.seg[i - first];
-                if (sg.n == 0) continue;
-                CrtCombineArgs c;
-                std::memset(&c, 0, sizeof(c));
-                c.Y = sg.Y;
-                c.C = L.C[i];
-                c.m = L.m;
-                c.n = sg.n;
-                c.nbc = sg.nbc;
-                c.plane = sg.plane;
-                c.ldc = L.ldc[i];
-                c.q = rights[i].q;
-                c.barrett = (uint64_t)((~(unsigned __int128)0 >> 64) / c.q);
-                c.Mq = (uint64_t)(M % c.q);
-                c.D = D;
-                for (int j = 0; j < D; ++j) {
-                    c.w[j] = (uint64_t)((M / (unsigned)kCrtModuli[j]) % c.q);
-                    c.pinv[j] = 1.0f / (float)kCrtModuli[j];
-                }
-                ProfScope ps("crt_combine", s);
-                if (launch_crt_combine(c, s) != hipSuccess) {
-                    release();
-                    return HLB_EDEVICE;
-                }
-            }
         }
     }
     release();
