@@ -66,11 +66,10 @@ _CSRC = os.path.join(ROOT, "paper_2503_16080_amd", "csrc")
 # SHA-256 they are valid for, and the kernel-name substring that selects their dispatches.
 TRAFFIC = {
     "crt_gemm": {"file": os.path.join(ROOT, "profiles", "crt_gemm_traffic.json"),
-                 # api.cpp decides how the work is cut into launches (per-dispatch counters)
-                 "sources": [os.path.join(_CSRC, f) for f in ("crt.hip", "crt.hpp", "common.hpp", "api.cpp")],
+                 "sources": [os.path.join(_CSRC, f) for f in ("crt.hip", "crt.hpp", "common.hpp")],
                  "match": "crt_gemm_kernel"},
     "gemm_i8": {"file": os.path.join(ROOT, "profiles", "gemm_i8_traffic.json"),
-                "sources": [os.path.join(_CSRC, f) for f in ("gemm_i8.hip", "i8_tile.hpp", "common.hpp", "api.cpp")],
+                "sources": [os.path.join(_CSRC, f) for f in ("gemm_i8.hip", "i8_tile.hpp", "common.hpp")],
                 "match": "gemm_i8_kernel"},
 }
 
