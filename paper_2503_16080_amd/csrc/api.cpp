@@ -389,10 +389,20 @@ hlb_status check_modulus(uint64_t q) { return (q >= 2 && q < kMaxModulus) ? HLB_
 // ---------------------------------------------------------------------------------------
 // Workspace: stream-ordered allocations from the device's default pool (kept cached).
 // ---------------------------------------------------------------------------------------
+// Sizes are rounded up to one of four steps per power of two (at most 25 % more), so that
+// calls of varying shapes ask the pool for few distinct sizes and reuse its cached blocks
+// instead of mapping new memory on every call.
+static size_t ws_bucket(size_t bytes) {
+    if (bytes <= ((size_t)1 << 16)) return (size_t)1 << 16;
+    int e = 63 - __builtin_clzll((unsigned long long)bytes);
+    const size_t step = (size_t)1 << (e - 2);
+    return (bytes + step - 1) / step * step;
+}
+
 hlb_status ws_alloc(void **p, size_t bytes, hipStream_t s) {
     *p = nullptr;
     if (bytes == 0) return HLB_OK;
-    if (hipMallocAsync(p, bytes, s) != hipSuccess) {
+    if (hipMallocAsync(p, ws_bucket(bytes), s) != hipSuccess) {
         (void)hipGetLastError();
         return HLB_ENOMEM;
     }
