@@ -176,10 +176,18 @@ typedef struct {
 /*
  * A batch of independent CP-MMs of uneven shapes that share the L primes (Theorem
  * th:pcmm-shs applied to each problem; the per-prime products are independent, as in
- * Section 6.1 Strategy 3).  All products run in ONE persistent kernel launch that pulls
- * output tiles from a work list (largest first), preceded by one digit-split launch for all
- * plaintexts and one for all ciphertext parts; the launch sequence is captured once per
- * distinct batch signature (shapes, pointers, primes) into a HIP graph and replayed.
+ * Section 6.1 Strategy 3).
+ *   form HLB_FORM_INT8 or HLB_FORM_AUTO (plaintexts within 3 digits, primes within 7): all
+ *     products run in ONE persistent kernel launch that pulls output tiles from a work list
+ *     (largest first), preceded by one digit-split launch for all plaintexts and one for all
+ *     ciphertext parts.
+ *   form HLB_FORM_INT8_CRT: one residue-split launch for every operand, one GEMM launch over
+ *     every (problem, modulus, tile) and one recombination launch, with the moduli count
+ *     planned for the largest K and plaintext bound of the batch.
+ *   other forms and plans run problem by problem through hlb_cp_mm.
+ * The launch sequence is captured once per distinct batch signature (shapes, pointers,
+ * primes, form) into a HIP graph and replayed (HLB_OPT_BATCH_GRAPH = 0: eager launches on a
+ * stream-ordered workspace, with a synchronization of `stream` before return).
  *   probs: host array of `count` problems (count >= 0).  Output buffers must not overlap.
  * Results are bit-identical to calling hlb_cp_mm on each problem.
  */

@@ -7,6 +7,11 @@
 // CU) pulls tiles from the counter, largest K first.  Each problem uses the tile class the
 // planner picks for its shape.  The four launches are captured once per batch signature
 // into a HIP graph and replayed on later calls with the same signature.
+//
+// Multimodular form (Strategy 3): one D for the whole batch (the planner's count for the
+// largest K and plaintext bound), one launch splits every left and right operand into its
+// residue planes, one GEMM launch covers every (problem, modulus, tile), one launch
+// recombines every output matrix; captured and replayed in the same way.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +26,7 @@
 #include "common.hpp"
 #include "host.hpp"
 #include "launch.hpp"
+#include "crt.hpp"
 
 namespace hlb {
 
@@ -245,6 +251,219 @@ hlb_status enqueue(const BatchLayout &lay, char *base, int grid, hipStream_t s) 
     return HLB_OK;
 }
 
+
+// ------------------------------- multimodular batch -------------------------------------
+struct CrtBatchLayout {
+    int D = 0;
+    CrtScale scale;
+    std::vector<CrtSplitJob> sjobs;
+    int64_t split_wgs = 0;
+    std::vector<CrtBatchProb> probs;
+    std::vector<CrtSeg> segs;
+    std::vector<CrtCombineJob> cjobs;
+    int64_t combine_wgs = 0;
+    int64_t total_items = 0;
+    // descriptor offsets, then the residue planes (offsets relative to off_planes) and the
+    // product planes (offsets relative to off_ybytes)
+    size_t off_sjobs = 0, off_probs = 0, off_segs = 0, off_cjobs = 0, off_planes = 0, off_ybytes = 0, bytes = 0;
+};
+
+hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint64_t *primes, int L,
+                            CrtBatchLayout &lay) {
+    uint64_t qmax = 0;
+    for (int l = 0; l < L; ++l) qmax = std::max(qmax, primes[l]);
+    int64_t kmax = 1, pmax = 1;
+    for (int i = 0; i < count; ++i) {
+        const hlb_cpmm_problem &p = probs[i];
+        if (p.m == 0 || p.k == 0 || (p.nA == 0 && p.nB == 0)) continue;
+        kmax = std::max(kmax, p.k);
+        pmax = std::max(pmax, p.p_absmax);
+    }
+    Plan pl;
+    pl.kind = 1;
+    hlb_status st = plan(1, kmax, qmax, pmax, HLB_FORM_INT8_CRT, &pl);
+    if (st != HLB_OK) return st;
+    const int D = pl.np;
+    lay.D = D;
+    unsigned __int128 M = 1;
+    for (int i = 0; i < D; ++i) M *= (unsigned)kCrtModuli[i];
+    std::memset(&lay.scale, 0, sizeof(lay.scale));
+    for (int i = 0; i < D; ++i) {
+        const int p = kCrtModuli[i];
+        const int mi = (int)((M / (unsigned)p) % (unsigned)p);
+        for (int v = 1; v < p; ++v)
+            if ((mi * v) % p == 1) {
+                lay.scale.s[i] = v;
+                break;
+            }
+    }
+
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].k > probs[b].k; });
+    const int64_t bn = crt_batch_tile_cols(), xsub = bn / 128;
+    const int64_t sub = (int64_t)D * 128 * kBK8;  // bytes of one 128-wide tile and k block
+    size_t plane_off = 0, y_off = 0;
+    for (int oi = 0; oi < count; ++oi) {
+        const hlb_cpmm_problem &p = probs[order[oi]];
+        if (p.m == 0 || p.k == 0 || (p.nA == 0 && p.nB == 0)) continue;
+        const int64_t kblocks = (p.k + kBK8 - 1) / kBK8;
+        const int64_t lt = ((p.m + 255) / 256) * 2, tiles_m = lt / 2;
+
+        CrtSplitJob pj;
+        std::memset(&pj, 0, sizeof(pj));
+        pj.wg_start = lay.split_wgs;
+        pj.src = p.P;
+        pj.ld = p.ldp;
+        pj.extent = p.m;
+        pj.k = p.k;
+        pj.qc = 0;
+        pj.kblocks = (int32_t)kblocks;
+        pj.rows_side = 1;
+        pj.out = (int8_t *)(uintptr_t)plane_off;
+        lay.sjobs.push_back(pj);
+        lay.split_wgs += lt * kblocks;
+        plane_off += (size_t)(lt * kblocks * sub);
+
+        CrtBatchProb bp;
+        std::memset(&bp, 0, sizeof(bp));
+        bp.item_start = lay.total_items;
+        bp.Pd = (const int8_t *)pj.out;
+        bp.Xd = (const int8_t *)(uintptr_t)plane_off;
+        bp.kblocks = (int32_t)kblocks;
+        bp.tiles_m = (int32_t)tiles_m;
+        bp.seg0 = (int32_t)lay.segs.size();
+        int64_t tb = 0;
+        for (int l = 0; l < L; ++l) {
+            for (int part = 0; part < 2; ++part) {
+                const int64_t n = part == 0 ? p.nA : p.nB;
+                if (n == 0) continue;
+                const uint64_t *X = (part == 0 ? p.A : p.B) + (int64_t)l * p.k * n;
+                uint64_t *C = (part == 0 ? p.PA : p.PB) + (int64_t)l * p.m * n;
+                const int64_t tg = (n + bn - 1) / bn;
+                CrtSplitJob xj;
+                std::memset(&xj, 0, sizeof(xj));
+                xj.wg_start = lay.split_wgs;
+                xj.src = X;
+                xj.ld = n;
+                xj.extent = n;
+                xj.k = p.k;
+                xj.qc = primes[l];
+                xj.kblocks = (int32_t)kblocks;
+                xj.rows_side = 0;
+                xj.out = (int8_t *)(uintptr_t)(plane_off + (size_t)(tb * xsub * kblocks * sub));
+                lay.sjobs.push_back(xj);
+                lay.split_wgs += tg * xsub * kblocks;
+
+                CrtSeg sg;
+                std::memset(&sg, 0, sizeof(sg));
+                sg.Y = (uint8_t *)(uintptr_t)y_off;
+                sg.n = n;
+                sg.nbc = tg * bn / 32;
+                sg.plane = (tiles_m * 256) * (tg * bn);
+                sg.tile_begin = (int32_t)tb;
+                lay.segs.push_back(sg);
+
+                CrtCombineJob cj;
+                std::memset(&cj, 0, sizeof(cj));
+                cj.wg_start = lay.combine_wgs;
+                CrtCombineArgs &c = cj.a;
+                c.Y = sg.Y;
+                c.C = C;
+                c.m = p.m;
+                c.n = n;
+                c.nbc = sg.nbc;
+                c.plane = sg.plane;
+                c.ldc = n;
+                c.q = primes[l];
+                c.barrett = (uint64_t)((~(unsigned __int128)0 >> 64) / c.q);
+                c.Mq = (uint64_t)(M % c.q);
+                c.D = D;
+                for (int j = 0; j < D; ++j) {
+                    c.w[j] = (uint64_t)((M / (unsigned)kCrtModuli[j]) % c.q);
+                    c.pinv[j] = 1.0f / (float)kCrtModuli[j];
+                }
+                lay.cjobs.push_back(cj);
+                lay.combine_wgs += crt_combine_wgs(p.m, n);
+                y_off += (size_t)(D * sg.plane);
+                tb += tg;
+            }
+        }
+        plane_off += (size_t)(tb * xsub * kblocks * sub);
+        const int64_t items = (int64_t)D * tiles_m * tb;
+        if (items > INT32_MAX / 2 || tb > INT32_MAX / 2) return HLB_EINVAL;
+        bp.tiles_n = (int32_t)tb;
+        bp.nseg = (int32_t)lay.segs.size() - bp.seg0;
+        lay.total_items += items;
+        lay.probs.push_back(bp);
+    }
+    if (lay.total_items > INT32_MAX || lay.split_wgs > INT32_MAX || lay.combine_wgs > INT32_MAX) return HLB_EINVAL;
+    size_t off = 0;
+    lay.off_sjobs = off;
+    off = align_up(off + lay.sjobs.size() * sizeof(CrtSplitJob), 256);
+    lay.off_probs = off;
+    off = align_up(off + lay.probs.size() * sizeof(CrtBatchProb), 256);
+    lay.off_segs = off;
+    off = align_up(off + lay.segs.size() * sizeof(CrtSeg), 256);
+    lay.off_cjobs = off;
+    off = align_up(off + lay.cjobs.size() * sizeof(CrtCombineJob), 256);
+    lay.off_planes = off;
+    lay.off_ybytes = align_up(off + plane_off, 256);
+    lay.bytes = lay.off_ybytes + y_off;
+    return HLB_OK;
+}
+
+// Turns plane offsets into device addresses inside a workspace at `base`.
+void rebase_crt(CrtBatchLayout &lay, char *base) {
+    char *planes = base + lay.off_planes, *ybytes = base + lay.off_ybytes;
+    for (CrtSplitJob &j : lay.sjobs) j.out = (int8_t *)(planes + (uintptr_t)j.out);
+    for (CrtBatchProb &p : lay.probs) {
+        p.Pd = (const int8_t *)(planes + (uintptr_t)p.Pd);
+        p.Xd = (const int8_t *)(planes + (uintptr_t)p.Xd);
+    }
+    for (CrtSeg &sg : lay.segs) sg.Y = (uint8_t *)(ybytes + (uintptr_t)sg.Y);
+    for (CrtCombineJob &j : lay.cjobs) j.a.Y = (const uint8_t *)(ybytes + (uintptr_t)j.a.Y);
+}
+
+std::vector<char> crt_descriptor_image(const CrtBatchLayout &lay) {
+    std::vector<char> img(lay.off_planes, 0);
+    std::memcpy(img.data() + lay.off_sjobs, lay.sjobs.data(), lay.sjobs.size() * sizeof(CrtSplitJob));
+    std::memcpy(img.data() + lay.off_probs, lay.probs.data(), lay.probs.size() * sizeof(CrtBatchProb));
+    std::memcpy(img.data() + lay.off_segs, lay.segs.data(), lay.segs.size() * sizeof(CrtSeg));
+    std::memcpy(img.data() + lay.off_cjobs, lay.cjobs.data(), lay.cjobs.size() * sizeof(CrtCombineJob));
+    return img;
+}
+
+// The three launches of a multimodular batch on stream s (capturable: kernels only).
+hlb_status enqueue_crt(const CrtBatchLayout &lay, char *base, hipStream_t s) {
+    int n_xcd = 8;
+    (void)device_ready(&n_xcd);
+    {
+        ProfScope ps("crt_split_batch", s);
+        if (launch_crt_split_batch(lay.D, (const CrtSplitJob *)(base + lay.off_sjobs), (int)lay.sjobs.size(),
+                                   lay.split_wgs, lay.scale, s) != hipSuccess)
+            return HLB_EDEVICE;
+    }
+    {
+        CrtBatchArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.probs = (const CrtBatchProb *)(base + lay.off_probs);
+        a.segs = (const CrtSeg *)(base + lay.off_segs);
+        a.total_items = lay.total_items;
+        a.nprob = (int32_t)lay.probs.size();
+        a.D = lay.D;
+        a.group_m = 4;
+        a.n_xcd = n_xcd;
+        ProfScope ps("crt_gemm_batch", s);
+        if (launch_crt_gemm_batch(a, s) != hipSuccess) return HLB_EDEVICE;
+    }
+    ProfScope ps("crt_combine_batch", s);
+    if (launch_crt_combine_batch((const CrtCombineJob *)(base + lay.off_cjobs), (int)lay.cjobs.size(), lay.combine_wgs,
+                                 s) != hipSuccess)
+        return HLB_EDEVICE;
+    return HLB_OK;
+}
+
 // ------------------------------- graph cache -------------------------------------------
 struct GraphEntry {
     hipGraph_t graph = nullptr;
@@ -285,6 +504,93 @@ std::vector<uint64_t> signature(const hlb_cpmm_problem *probs, int count, const 
         sig.insert(sig.end(), f, f + 11);
     }
     return sig;
+}
+
+// Key of a cached multimodular batch graph: a tag, device, stream, D, the primes and every
+// problem field.
+std::vector<uint64_t> crt_signature(const hlb_cpmm_problem *probs, int count, const uint64_t *primes, int L, int dev,
+                                    hipStream_t s, int D) {
+    std::vector<uint64_t> sig;
+    sig.reserve((size_t)count * 11 + L + 8);
+    sig.push_back(0x4352544241544348ull);  // distinguishes these keys from the digit batch's
+    sig.push_back((uint64_t)dev);
+    sig.push_back((uint64_t)(uintptr_t)s);
+    sig.push_back((uint64_t)D);
+    sig.push_back((uint64_t)L);
+    for (int l = 0; l < L; ++l) sig.push_back(primes[l]);
+    for (int i = 0; i < count; ++i) {
+        const hlb_cpmm_problem &p = probs[i];
+        const uint64_t f[] = {(uint64_t)p.m, (uint64_t)p.k, (uint64_t)p.nA, (uint64_t)p.nB, (uint64_t)(uintptr_t)p.P,
+                              (uint64_t)p.ldp, (uint64_t)p.p_absmax, (uint64_t)(uintptr_t)p.A,
+                              (uint64_t)(uintptr_t)p.B, (uint64_t)(uintptr_t)p.PA, (uint64_t)(uintptr_t)p.PB};
+        sig.insert(sig.end(), f, f + 11);
+    }
+    return sig;
+}
+
+// A multimodular batch: eager (stream-ordered workspace, descriptors uploaded, three
+// launches), or captured once per signature into a cached graph with its own workspace.
+hlb_status run_crt_batch(const hlb_cpmm_problem *probs, int count, const uint64_t *primes, int L, hipStream_t s) {
+    CrtBatchLayout lay;
+    hlb_status st = build_crt_layout(probs, count, primes, L, lay);
+    if (st != HLB_OK) return st;
+    if (lay.total_items == 0) return HLB_OK;
+    if (!opt_batch_graph()) {
+        void *ws = nullptr;
+        if ((st = ws_alloc(&ws, lay.bytes, s)) != HLB_OK) return st;
+        rebase_crt(lay, (char *)ws);
+        std::vector<char> img = crt_descriptor_image(lay);
+        if (hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, s) != hipSuccess) st = HLB_EDEVICE;
+        if (st == HLB_OK) st = enqueue_crt(lay, (char *)ws, s);
+        // the host image must outlive the copy
+        if (hipStreamSynchronize(s) != hipSuccess && st == HLB_OK) st = HLB_EDEVICE;
+        ws_free(ws, s);
+        return st;
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const std::vector<uint64_t> sig = crt_signature(probs, count, primes, L, dev, s, lay.D);
+    std::lock_guard<std::mutex> g(g_graph_mu);
+    auto it = g_graphs.find(sig);
+    if (it == g_graphs.end()) {
+        if (g_graphs.size() >= kMaxGraphs) {
+            if (hipStreamSynchronize(s) != hipSuccess) return HLB_EDEVICE;
+            for (auto &kv : g_graphs) destroy_entry(kv.second);
+            g_graphs.clear();
+        }
+        GraphEntry e;
+        if (hipMalloc((void **)&e.ws, lay.bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return HLB_ENOMEM;
+        }
+        rebase_crt(lay, e.ws);
+        std::vector<char> img = crt_descriptor_image(lay);
+        if (hipMemcpy(e.ws, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            destroy_entry(e);
+            return HLB_EDEVICE;
+        }
+        hipStream_t cap = nullptr;
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+            destroy_entry(e);
+            return HLB_EDEVICE;
+        }
+        hlb_status cst = HLB_OK;
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) cst = HLB_EDEVICE;
+        if (cst == HLB_OK) {
+            cst = enqueue_crt(lay, e.ws, cap);
+            if (hipStreamEndCapture(cap, &e.graph) != hipSuccess && cst == HLB_OK) cst = HLB_EDEVICE;
+        }
+        (void)hipStreamDestroy(cap);
+        if (cst == HLB_OK && hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess)
+            cst = HLB_EDEVICE;
+        if (cst != HLB_OK) {
+            (void)hipGetLastError();
+            destroy_entry(e);
+            return cst;
+        }
+        it = g_graphs.emplace(sig, e).first;
+    }
+    return hipGraphLaunch(it->second.exec, s) == hipSuccess ? HLB_OK : HLB_EDEVICE;
 }
 
 int persistent_grid(const BatchLayout &lay) {
@@ -344,7 +650,8 @@ extern "C" hlb_status hlb_cp_mm_batch(const hlb_cpmm_problem *probs, int count, 
     uint64_t qmax = 0;
     for (int l = 0; l < L; ++l) qmax = std::max(qmax, primes[l]);
     if (i8_digits_for(qmax - 1) > 7) persistent = false;
-    if (!persistent) {
+    const bool multimodular = form == HLB_FORM_INT8_CRT;
+    if (!persistent && !multimodular) {
         for (const hlb_cpmm_problem &p : local) {
             st = hlb_cp_mm(p.m, p.k, p.nA, p.nB, p.P, p.ldp, p.p_absmax, p.A, p.B, primes, L, p.PA, p.PB, form, stream);
             if (st != HLB_OK) return st;
@@ -362,6 +669,7 @@ extern "C" hlb_status hlb_cp_mm_batch(const hlb_cpmm_problem *probs, int count, 
         }
     }
 
+    if (multimodular) return run_crt_batch(local.data(), count, primes, L, s);
     BatchLayout lay;
     if ((st = build_layout(local.data(), count, primes, L, lay)) != HLB_OK) return st;
     if (lay.total_items == 0) return HLB_OK;

@@ -67,12 +67,11 @@ __device__ __forceinline__ int64_t crt_centred(uint64_t x, uint64_t qc) {
     return (qc != 0 && 2 * x > qc) ? (int64_t)x - (int64_t)qc : (int64_t)x;
 }
 
-// grid: (tiles * kblocks) workgroups of 512 threads = 128 rows x 4 chunks
+// One (128-row tile, k block) of a left operand: 512 threads = 128 rows x 4 chunks.
 template <int D>
-__global__ __launch_bounds__(512) void crt_split_rows(const int64_t *__restrict__ P, int64_t ldp, int64_t m,
-                                                      int64_t k, int kblocks, uint64_t qc, const CrtScale scale,
-                                                      int8_t *__restrict__ out) {
-    const int tile = blockIdx.x / kblocks, kb = blockIdx.x % kblocks;
+__device__ __forceinline__ void crt_split_rows_tile(const int64_t *__restrict__ P, int64_t ldp, int64_t m, int64_t k,
+                                                    int kblocks, int tile, int kb, uint64_t qc, const CrtScale &scale,
+                                                    int8_t *__restrict__ out) {
     const int r = threadIdx.x >> 2, c = threadIdx.x & 3;
     const int64_t row = (int64_t)tile * kCrtR + r;
     const int64_t k0 = (int64_t)kb * kBK8 + c * 16;
@@ -88,10 +87,11 @@ __global__ __launch_bounds__(512) void crt_split_rows(const int64_t *__restrict_
     crt_store_chunk<D, true>(v, out + ((int64_t)tile * kblocks + kb) * (D * kCrtR * kBK8), r, c, scale);
 }
 
+// One (128-column tile, k block) of a right operand.
 template <int D>
-__global__ __launch_bounds__(512) void crt_split_cols(const uint64_t *__restrict__ X, int64_t ldx, int64_t k,
-                                                      int64_t n, int kblocks, uint64_t qc, int8_t *__restrict__ out) {
-    const int tile = blockIdx.x / kblocks, kb = blockIdx.x % kblocks;
+__device__ __forceinline__ void crt_split_cols_tile(const uint64_t *__restrict__ X, int64_t ldx, int64_t k, int64_t n,
+                                                    int kblocks, int tile, int kb, uint64_t qc,
+                                                    int8_t *__restrict__ out) {
     const int r = threadIdx.x >> 2, c = threadIdx.x & 3;
     const int64_t col = (int64_t)tile * kCrtR + r;
     const int64_t k0 = (int64_t)kb * kBK8 + c * 16;
@@ -105,6 +105,48 @@ __global__ __launch_bounds__(512) void crt_split_cols(const uint64_t *__restrict
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = (col < n && k0 + e < k) ? crt_centred(x[e], qc) : 0;
     crt_store_chunk<D, false>(v, out + ((int64_t)tile * kblocks + kb) * (D * kCrtR * kBK8), r, c, CrtScale{});
+}
+
+// grid: (tiles * kblocks) workgroups of 512 threads
+template <int D>
+__global__ __launch_bounds__(512) void crt_split_rows(const int64_t *__restrict__ P, int64_t ldp, int64_t m,
+                                                      int64_t k, int kblocks, uint64_t qc, const CrtScale scale,
+                                                      int8_t *__restrict__ out) {
+    crt_split_rows_tile<D>(P, ldp, m, k, kblocks, blockIdx.x / kblocks, blockIdx.x % kblocks, qc, scale, out);
+}
+
+template <int D>
+__global__ __launch_bounds__(512) void crt_split_cols(const uint64_t *__restrict__ X, int64_t ldx, int64_t k,
+                                                      int64_t n, int kblocks, uint64_t qc, int8_t *__restrict__ out) {
+    crt_split_cols_tile<D>(X, ldx, k, n, kblocks, blockIdx.x / kblocks, blockIdx.x % kblocks, qc, out);
+}
+
+// Index of the job owning workgroup w: the last job whose wg_start is <= w (binary search;
+// jobs in increasing wg_start, the first at 0).
+template <class J>
+__device__ __forceinline__ int crt_job_of(const J *__restrict__ jobs, int njobs, int64_t w) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].wg_start <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Many operands in one launch (left operands are scaled by `scale`, right operands centred
+// modulo their job's modulus).
+template <int D>
+__global__ __launch_bounds__(512) void crt_split_batch(const CrtSplitJob *__restrict__ jobs, int njobs,
+                                                       const CrtScale scale) {
+    const int64_t w = blockIdx.x;
+    const CrtSplitJob &j = jobs[crt_job_of(jobs, njobs, w)];
+    const int64_t local = w - j.wg_start;
+    const int tile = (int)(local / j.kblocks), kb = (int)(local % j.kblocks);
+    if (j.rows_side)
+        crt_split_rows_tile<D>((const int64_t *)j.src, j.ld, j.extent, j.k, j.kblocks, tile, kb, j.qc, scale, j.out);
+    else
+        crt_split_cols_tile<D>((const uint64_t *)j.src, j.ld, j.k, j.extent, j.kblocks, tile, kb, j.qc, j.out);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -146,31 +188,18 @@ __device__ __forceinline__ uint32_t crt_y(int c, int p, int c16, float pinv) {
     return (uint32_t)r;
 }
 
+// One 256 x BN output tile of one modulus: the K loop over the plane blocks at gP (left, two
+// 128-row blocks tile_stride apart) and gX (right, XSUB 128-column blocks), then the epilogue
+// into the modulus' product plane Y (block rows from brt, block columns from bct).
 template <class T>
-__global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_kernel(const CrtGemmArgs args) {
+__device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const int8_t *gX, int KB, int64_t plane_stride,
+                                         int p, uint8_t *Y, int64_t nbc, int64_t brt, int64_t bct) {
     constexpr int MB = T::MB, NB = T::NB, kCrtThreads = T::THREADS, kCrtWavesN = T::WN;
     constexpr int kCrtNbuf = T::NBUF;
-    __shared__ __attribute__((aligned(16))) int8_t lds[kCrtNbuf * T::STAGE];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave_u / kCrtWavesN, wn = wave_u % kCrtWavesN;
-
-    // the D moduli stack as D row bands of one (D * tiles_m) x tiles_n grid
-    const int total = args.D * args.tiles_m * args.tiles_n;
-    int rbv, cb;
-    map_tile(blockIdx.x, total, args.n_xcd, args.D * args.tiles_m, args.tiles_n, args.group_m, rbv, cb);
-    const int mi = rbv / args.tiles_m, rb = rbv % args.tiles_m;
-    int si = 0;
-#pragma unroll 1
-    for (int i = 1; i < args.nseg; ++i)
-        if (cb >= args.seg[i].tile_begin) si = i;
-    const CrtSeg &sg = args.seg[si];
-
-    const int KB = args.kblocks;
-    const int64_t plane_stride = (int64_t)args.D * kCrtSub;  // bytes of one k block of a 128-wide tile
     const int64_t tile_stride = (int64_t)KB * plane_stride;  // bytes of one 128-wide tile
-    const int8_t *gP = args.Pd + (int64_t)(2 * rb) * tile_stride + (int64_t)mi * kCrtSub;
-    const int8_t *gX = args.Xd + (int64_t)(cb * T::XSUB) * tile_stride + (int64_t)mi * kCrtSub;
 
     v16i acc[MB][NB];
 #pragma unroll
@@ -263,12 +292,10 @@ __global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_kernel(const CrtGemmAr
     }
 
     // epilogue: one 16-byte store per 32 x 32 block and lane (the plane covers whole tiles)
-    const int p = kCrtModuli[mi];
     const int c16 = (1 << 16) % p;
     const float pinv = 1.0f / (float)p;
-    const int64_t br0 = (int64_t)rb * (kCrtBM / 32) + wm * MB;
-    const int64_t bc0 = (int64_t)(cb - sg.tile_begin) * (T::BN / 32) + wn * NB;
-    uint8_t *Y = sg.Y + (int64_t)mi * sg.plane;
+    const int64_t br0 = brt + wm * MB;
+    const int64_t bc0 = bct + wn * NB;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -276,9 +303,72 @@ __global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_kernel(const CrtGemmAr
             uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
             for (int r = 0; r < 16; ++r) w[r >> 2] |= crt_y(acc[mb][nb][r], p, c16, pinv) << (8 * (r & 3));
-            const int64_t blk = (br0 + mb) * sg.nbc + bc0 + nb;
+            const int64_t blk = (br0 + mb) * nbc + bc0 + nb;
             *(uint4 *)(Y + (blk * 64 + lane) * 16) = uint4{w[0], w[1], w[2], w[3]};
         }
+}
+
+template <class T>
+__global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_kernel(const CrtGemmArgs args) {
+    __shared__ __attribute__((aligned(16))) int8_t lds[T::NBUF * T::STAGE];
+    // the D moduli stack as D row bands of one (D * tiles_m) x tiles_n grid
+    const int total = args.D * args.tiles_m * args.tiles_n;
+    int rbv, cb;
+    map_tile(blockIdx.x, total, args.n_xcd, args.D * args.tiles_m, args.tiles_n, args.group_m, rbv, cb);
+    const int mi = rbv / args.tiles_m, rb = rbv % args.tiles_m;
+    int si = 0;
+#pragma unroll 1
+    for (int i = 1; i < args.nseg; ++i)
+        if (cb >= args.seg[i].tile_begin) si = i;
+    const CrtSeg &sg = args.seg[si];
+    const int KB = args.kblocks;
+    const int64_t plane_stride = (int64_t)args.D * kCrtSub;  // bytes of one k block of a 128-wide tile
+    const int64_t tile_stride = (int64_t)KB * plane_stride;
+    crt_tile<T>(lds, args.Pd + (int64_t)(2 * rb) * tile_stride + (int64_t)mi * kCrtSub,
+                args.Xd + (int64_t)(cb * T::XSUB) * tile_stride + (int64_t)mi * kCrtSub, KB, plane_stride,
+                kCrtModuli[mi], sg.Y + (int64_t)mi * sg.plane, sg.nbc, (int64_t)rb * (kCrtBM / 32),
+                (int64_t)(cb - sg.tile_begin) * (T::BN / 32));
+}
+
+// A batch of problems in one launch: workgroup w takes work item w (remapped so that each XCD
+// holds a contiguous run of items), finds its problem by binary search over the problems'
+// first items, and its tile within the problem in the raster of crt_gemm_kernel.
+template <class T>
+__global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_batch_kernel(const CrtBatchArgs args) {
+    __shared__ __attribute__((aligned(16))) int8_t lds[T::NBUF * T::STAGE];
+    int64_t t = blockIdx.x;
+    if (args.n_xcd > 1) {
+        const int64_t per = args.total_items / args.n_xcd, rem = args.total_items % args.n_xcd;
+        const int64_t x = t % args.n_xcd, local = t / args.n_xcd;
+        t = (x < rem) ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+    }
+    int lo = 0, hi = args.nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (args.probs[mid].item_start <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const CrtBatchProb &pb = args.probs[lo];
+    const int local = (int)(t - pb.item_start);
+    const int tm_all = args.D * pb.tiles_m;
+    const int span = args.group_m * pb.tiles_n;
+    const int gi = local / span, first = gi * args.group_m;
+    const int gm = min(args.group_m, tm_all - first);
+    const int in = local - gi * span;
+    const int rbv = first + in % gm, cb = in / gm;
+    const int mi = rbv / pb.tiles_m, rb = rbv % pb.tiles_m;
+    int si = pb.seg0;
+#pragma unroll 1
+    for (int i = pb.seg0 + 1; i < pb.seg0 + pb.nseg; ++i)
+        if (cb >= args.segs[i].tile_begin) si = i;
+    const CrtSeg &sg = args.segs[si];
+    const int KB = pb.kblocks;
+    const int64_t plane_stride = (int64_t)args.D * kCrtSub;
+    const int64_t tile_stride = (int64_t)KB * plane_stride;
+    crt_tile<T>(lds, pb.Pd + (int64_t)(2 * rb) * tile_stride + (int64_t)mi * kCrtSub,
+                pb.Xd + (int64_t)(cb * T::XSUB) * tile_stride + (int64_t)mi * kCrtSub, KB, plane_stride,
+                kCrtModuli[mi], sg.Y + (int64_t)mi * sg.plane, sg.nbc, (int64_t)rb * (kCrtBM / 32),
+                (int64_t)(cb - sg.tile_begin) * (T::BN / 32));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -298,51 +388,72 @@ __device__ __forceinline__ uint64_t reduce_u64(uint64_t x, uint64_t q, uint64_t 
 // three 20-bit limbs of w_i (each limb sum stays below 2^32, 24-bit multiply-adds), and the
 // rounding t = round(sum_i y_i / p_i) needs only single precision: the fraction lies within
 // 1/4 of an integer, far beyond its rounding error.  (t M) mod q comes from a table in LDS.
-__global__ __launch_bounds__(kThreads) void crt_combine_kernel(const CrtCombineArgs a) {
-    __shared__ uint64_t tmq[kCrtMaxModuli + 1];
+__device__ __forceinline__ void crt_tmq_table(const CrtCombineArgs &a, uint64_t *tmq) {
     if (threadIdx.x <= (unsigned)a.D) tmq[threadIdx.x] = reduce_u64((uint64_t)threadIdx.x * a.Mq, a.q, a.barrett);
     __syncthreads();
-    const int64_t nbr = (a.m + 31) >> 5, nbc_valid = (a.n + 31) >> 5;
-    const int64_t total = nbr * nbc_valid * 64;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int lane = (int)(g & 63);
-        const int64_t b = g >> 6, br = b / nbc_valid, bc = b - br * nbc_valid;
-        const uint8_t *y = a.Y + ((br * a.nbc + bc) * 64 + lane) * 16;
-        uint32_t s0[16], s1[16], s2[16];
-        float f[16];
+}
+
+// Entries g of one output matrix (g = 64 * (32 x 32 block) + lane, g < 64 * blocks).
+__device__ __forceinline__ void crt_combine_lane(const CrtCombineArgs &a, const uint64_t *tmq, int64_t g,
+                                                 int64_t nbc_valid) {
+    const int lane = (int)(g & 63);
+    const int64_t b = g >> 6, br = b / nbc_valid, bc = b - br * nbc_valid;
+    const uint8_t *y = a.Y + ((br * a.nbc + bc) * 64 + lane) * 16;
+    uint32_t s0[16], s1[16], s2[16];
+    float f[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            s0[e] = s1[e] = s2[e] = 0u;
-            f[e] = 0.f;
-        }
+    for (int e = 0; e < 16; ++e) {
+        s0[e] = s1[e] = s2[e] = 0u;
+        f[e] = 0.f;
+    }
 #pragma unroll 2
-        for (int i = 0; i < a.D; ++i) {
-            const uint4 v = *(const uint4 *)(y + (int64_t)i * a.plane);
-            const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
-            const uint64_t w = a.w[i];
-            const uint32_t w0 = (uint32_t)w & 0xfffffu, w1 = (uint32_t)(w >> 20) & 0xfffffu, w2 = (uint32_t)(w >> 40);
-            const float pi = a.pinv[i];
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const uint32_t byte = (vw[e >> 2] >> (8 * (e & 3))) & 0xffu;
-                s0[e] += __umul24(byte, w0);
-                s1[e] += __umul24(byte, w1);
-                s2[e] += __umul24(byte, w2);
-                f[e] = __builtin_fmaf((float)byte, pi, f[e]);
-            }
-        }
-        const int64_t col = bc * 32 + (lane & 31);
-        if (col >= a.n) continue;
+    for (int i = 0; i < a.D; ++i) {
+        const uint4 v = *(const uint4 *)(y + (int64_t)i * a.plane);
+        const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+        const uint64_t w = a.w[i];
+        const uint32_t w0 = (uint32_t)w & 0xfffffu, w1 = (uint32_t)(w >> 20) & 0xfffffu, w2 = (uint32_t)(w >> 40);
+        const float pi = a.pinv[i];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const int64_t row = br * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-            if (row >= a.m) continue;
-            const uint64_t sum = ((uint64_t)s2[e] << 40) + ((uint64_t)s1[e] << 20) + s0[e];
-            const uint64_t sr = reduce_u64(sum, a.q, a.barrett);
-            const uint64_t tm = tmq[(int)__builtin_floorf(f[e] + 0.5f)];
-            a.C[row * a.ldc + col] = sr >= tm ? sr - tm : sr + a.q - tm;
+            const uint32_t byte = (vw[e >> 2] >> (8 * (e & 3))) & 0xffu;
+            s0[e] += __umul24(byte, w0);
+            s1[e] += __umul24(byte, w1);
+            s2[e] += __umul24(byte, w2);
+            f[e] = __builtin_fmaf((float)byte, pi, f[e]);
         }
     }
+    const int64_t col = bc * 32 + (lane & 31);
+    if (col >= a.n) return;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int64_t row = br * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (row >= a.m) continue;
+        const uint64_t sum = ((uint64_t)s2[e] << 40) + ((uint64_t)s1[e] << 20) + s0[e];
+        const uint64_t sr = reduce_u64(sum, a.q, a.barrett);
+        const uint64_t tm = tmq[(int)__builtin_floorf(f[e] + 0.5f)];
+        a.C[row * a.ldc + col] = sr >= tm ? sr - tm : sr + a.q - tm;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void crt_combine_kernel(const CrtCombineArgs a) {
+    __shared__ uint64_t tmq[kCrtMaxModuli + 1];
+    crt_tmq_table(a, tmq);
+    const int64_t nbc_valid = (a.n + 31) >> 5;
+    const int64_t total = ((a.m + 31) >> 5) * nbc_valid * 64;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x)
+        crt_combine_lane(a, tmq, g, nbc_valid);
+}
+
+// Many output matrices in one launch: each workgroup serves kThreads entry groups of the job
+// that owns it.
+__global__ __launch_bounds__(kThreads) void crt_combine_batch(const CrtCombineJob *__restrict__ jobs, int njobs) {
+    __shared__ uint64_t tmq[kCrtMaxModuli + 1];
+    const CrtCombineJob &j = jobs[crt_job_of(jobs, njobs, blockIdx.x)];
+    crt_tmq_table(j.a, tmq);
+    const int64_t nbc_valid = (j.a.n + 31) >> 5;
+    const int64_t total = ((j.a.m + 31) >> 5) * nbc_valid * 64;
+    const int64_t g = ((int64_t)blockIdx.x - j.wg_start) * kThreads + threadIdx.x;
+    if (g < total) crt_combine_lane(j.a, tmq, g, nbc_valid);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -401,6 +512,36 @@ hipError_t launch_crt_combine(const CrtCombineArgs &a, hipStream_t s) {
     int64_t g = (threads + kThreads - 1) / kThreads;
     g = g > (1 << 20) ? (1 << 20) : g;
     hipLaunchKernelGGL(crt_combine_kernel, dim3((unsigned)g), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+int64_t crt_combine_wgs(int64_t m, int64_t n) { return (((m + 31) / 32) * ((n + 31) / 32) * 64 + kThreads - 1) / kThreads; }
+
+hipError_t launch_crt_split_batch(int D, const CrtSplitJob *jobs, int njobs, int64_t total_wgs, const CrtScale &scale,
+                                  hipStream_t s) {
+    if (total_wgs <= 0 || njobs <= 0) return hipSuccess;
+    if (total_wgs > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 g((unsigned)total_wgs), b(512);
+#define HLB_CASE(DD) \
+    if (D == DD) { hipLaunchKernelGGL(crt_split_batch<DD>, g, b, 0, s, jobs, njobs, scale); return hipGetLastError(); }
+    HLB_CRT_D(HLB_CASE)
+#undef HLB_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_crt_gemm_batch(const CrtBatchArgs &a, hipStream_t s) {
+    if (a.total_items <= 0) return hipSuccess;
+    if (a.total_items > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(crt_gemm_batch_kernel<CrtWide>, dim3((unsigned)a.total_items), dim3(CrtWide::THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+int crt_batch_tile_cols() { return CrtWide::BN; }
+
+hipError_t launch_crt_combine_batch(const CrtCombineJob *jobs, int njobs, int64_t total_wgs, hipStream_t s) {
+    if (total_wgs <= 0 || njobs <= 0) return hipSuccess;
+    if (total_wgs > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(crt_combine_batch, dim3((unsigned)total_wgs), dim3(kThreads), 0, s, jobs, njobs);
     return hipGetLastError();
 }
 

@@ -92,6 +92,43 @@ struct CrtCombineArgs {
     int32_t D, pad;
 };
 
+// One operand of a batched residue split: a left operand (rows_side = 1: extent rows of k
+// signed values, row stride ld) or a right operand (rows_side = 0: k rows of extent
+// residues, row stride ld, centred modulo qc).  Its workgroups are [wg_start, wg_start +
+// 128-wide tiles * kblocks).
+struct CrtSplitJob {
+    int64_t wg_start;
+    const void *src;
+    int64_t ld, extent, k;
+    uint64_t qc;
+    int32_t kblocks, rows_side;
+    int8_t *out;
+};
+
+// A problem of a multimodular batch: its plane workspaces, its GEMM tiles (D * tiles_m row
+// bands x tiles_n column tiles, items [item_start, item_start + D tiles_m tiles_n)) and its
+// output segments seg0 .. seg0 + nseg - 1 (right operands in order; their planes follow
+// one another from Xd).
+struct CrtBatchProb {
+    int64_t item_start;
+    const int8_t *Pd;
+    const int8_t *Xd;
+    int32_t kblocks, tiles_m, tiles_n, seg0, nseg, pad;
+};
+
+struct CrtBatchArgs {
+    const CrtBatchProb *probs;
+    const CrtSeg *segs;
+    int64_t total_items;
+    int32_t nprob, D, group_m, n_xcd;
+};
+
+// A recombination job of a batch: the output matrix's arguments and its first workgroup.
+struct CrtCombineJob {
+    int64_t wg_start;
+    CrtCombineArgs a;
+};
+
 // Factors applied to the left operand's residues in the split: (M / p_i)^{-1} mod p_i.
 struct CrtScale {
     int32_t s[kCrtMaxModuli];

@@ -65,6 +65,18 @@ struct CrtCombineArgs;
 int crt_tile_cols(int variant);
 hipError_t launch_crt_gemm(int variant, const CrtGemmArgs &a, hipStream_t s);
 hipError_t launch_crt_combine(const CrtCombineArgs &a, hipStream_t s);
+// Batched forms: one launch for many operands (jobs in increasing wg_start), one GEMM launch
+// for many problems (256 x crt_batch_tile_cols() tiles), one launch for many recombinations
+// (crt_combine_wgs workgroups each).
+struct CrtSplitJob;
+struct CrtBatchArgs;
+struct CrtCombineJob;
+hipError_t launch_crt_split_batch(int D, const CrtSplitJob *jobs, int njobs, int64_t total_wgs, const CrtScale &scale,
+                                  hipStream_t s);
+int crt_batch_tile_cols();
+hipError_t launch_crt_gemm_batch(const CrtBatchArgs &a, hipStream_t s);
+int64_t crt_combine_wgs(int64_t m, int64_t n);
+hipError_t launch_crt_combine_batch(const CrtCombineJob *jobs, int njobs, int64_t total_wgs, hipStream_t s);
 
 // Auxiliary kernels.
 hipError_t launch_validate(const uint64_t *X, int64_t rows, int64_t cols, int64_t ld, uint64_t q,

@@ -157,7 +157,7 @@ def test_auto_picks_form_by_shape():
 
 
 def test_batch_in_multimodular_form():
-    # a batch in the multimodular form runs problem by problem; results as for the oracle
+    # a batch in the multimodular form: one batched split, GEMM and recombination launch
     primes = wl.ntt_primes(45, 2)
     g = wl.rng(5600)
     probs, want = [], []
@@ -172,3 +172,41 @@ def test_batch_in_multimodular_form():
     hlb.cp_mm_batch(probs, primes, form="int8_crt")
     for p, (wA, wB) in zip(probs, want):
         assert np.array_equal(_np(p["PA"]), wA) and np.array_equal(_np(p["PB"]), wB)
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_batch_multimodular_replays_and_degenerate_members(graph):
+    # graph-cached and eager batches; a replay after the inputs change (same pointers) must
+    # follow them; members with k = 0, m = 0, one empty part, and sizes off every tile edge
+    primes = wl.ntt_primes(50, 3, skip=2)
+    g = wl.rng(5800 + graph)
+    shapes = [(130, 70, 33, 257), (0, 64, 64, 64), (65, 0, 40, 40), (300, 129, 0, 130), (257, 1000, 500, 0),
+              (33, 64, 300, 1)]
+    host, probs = [], []
+    for m, k, nA, nB in shapes:
+        P = wl.plaintext_matrix(g, m, k)
+        A = np.stack([wl.uniform_residues(g, (k, nA), q) for q in primes])
+        B = np.stack([wl.uniform_residues(g, (k, nB), q) for q in primes])
+        host.append([P, A, B])
+        probs.append(dict(P=_t(P), A=_t(A), B=_t(B), p_absmax=1 << 20,
+                          PA=torch.full((3, m, nA), -1, dtype=torch.int64, device=DEV),
+                          PB=torch.full((3, m, nB), -1, dtype=torch.int64, device=DEV)))
+    hlb.set_option(hlb.OPT_BATCH_GRAPH, graph)
+    try:
+        for rnd in range(2):
+            if rnd == 1:
+                # new values in the same buffers
+                for (P, A, B), pr in zip(host, probs):
+                    P[...] = wl.plaintext_matrix(g, *P.shape)
+                    for i, q in enumerate(primes):
+                        A[i] = wl.uniform_residues(g, A.shape[1:], q)
+                        B[i] = wl.uniform_residues(g, B.shape[1:], q)
+                    pr["P"].copy_(_t(P))
+                    pr["A"].copy_(_t(A))
+                    pr["B"].copy_(_t(B))
+            hlb.cp_mm_batch(probs, primes, form="int8_crt")
+            for (P, A, B), pr in zip(host, probs):
+                wA, wB = oracle.cp_mm(P, A, B, primes)
+                assert np.array_equal(_np(pr["PA"]), wA) and np.array_equal(_np(pr["PB"]), wB)
+    finally:
+        hlb.set_option(hlb.OPT_BATCH_GRAPH, 1)
