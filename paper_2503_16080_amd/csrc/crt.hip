@@ -5,8 +5,8 @@
 // every modular product is one exact INT8 -> INT32 matrix product:
 //   1. split: the centred operands (plaintext as signed integers; residues x mod q taken in
 //      (-q/2, q/2]) become D planes of balanced residues modulo p_0 .. p_{D-1} <= 256, in the
-//      tile-major, swizzled layout of the digit split ([tile][k block][plane][128][64]);
-//      The left operand's residues are multiplied by (M / p_i)^{-1} mod p_i in the split;
+//      tile-major, swizzled layout of the digit split ([tile][k block][plane][128][64]), the
+//      left operand's residues multiplied by (M / p_i)^{-1} mod p_i;
 //   2. GEMM: one plain INT8 product per modulus and output tile (v_mfma_i32_32x32x32_i8),
 //      |c| <= k 2^14 < 2^31; by the factor above, the byte y_i = c mod p_i is already the
 //      CRT coefficient, and the epilogue writes it in the accumulator order (crt.hpp);
@@ -14,6 +14,8 @@
 //      integer product as long as M > 2 |V|, and V mod q is formed from w_i = (M / p_i) mod q.
 // D moduli replace the DP * DX digit products of Strategy 1 (11 instead of 21 for a 20-bit
 // plaintext and 50-bit primes at k = 8192; 15 instead of 49 for two full residue operands).
+// Each stage has a batched kernel too: many operands, problems or output matrices in one
+// launch, found from job tables by binary search.
 #include "common.hpp"
 #include "crt.hpp"
 #include "launch.hpp"
@@ -153,8 +155,8 @@ __global__ __launch_bounds__(512) void crt_split_batch(const CrtSplitJob *__rest
 // 2. One INT8 product per modulus on a 256 x BN output tile: WM x WN waves, each owning
 //    MB x NB blocks of 32 x 32 outputs (WM * MB * 32 = 256).  Variants (tile, waves, block
 //    per wave): 256 x 128 with 8 waves of 64 x 64; 256 x 256 with 8 waves of 64 x 128.
-//    (A wave of 128 x 128 would need 256 accumulator registers plus its fragments, more than
-//    the register file holds without spilling in the main loop.)
+//    (Four waves of 128 x 128 need their 256 accumulators in AGPRs and leave one wave per
+//    SIMD, which hides less latency: measured slower.)
 // ---------------------------------------------------------------------------------------
 constexpr int kCrtBM = 256;
 constexpr int kCrtSub = kCrtR * kBK8;  // bytes of one plane block (128 x 64)
