@@ -30,7 +30,9 @@ def _np(t):
 @pytest.mark.parametrize("wide", [1, 0])
 @pytest.mark.parametrize("dims", [(1, 1, 1, 1, 1), (33, 65, 17, 40, 1), (256, 128, 128, 128, 2),
                                   (200, 300, 130, 70, 3), (300, 64, 257, 1, 4), (64, 700, 64, 0, 2),
-                                  (513, 129, 255, 129, 1), (100, 200, 600, 300, 1)])
+                                  (513, 129, 255, 129, 1), (100, 200, 600, 300, 1),
+                                  # 18 output matrices: more than one GEMM launch's segments
+                                  (70, 90, 40, 33, 9)])
 def test_cp_mm_crt_vs_oracle(dims, wide):
     m, k, nA, nB, L = dims
     w = wl.cpmm_uniform(5000 + sum(dims), m, k, max(nA, nB, 1), 50, L)
