@@ -62,16 +62,20 @@ def _parse():
 
 
 _CSRC = os.path.join(ROOT, "paper_2503_16080_amd", "csrc")
-# Counter summaries per GEMM kernel: the file bench.py reads them from, the sources whose
-# SHA-256 they are valid for, and the kernel-name substring that selects their dispatches.
+# Counter summaries per GEMM kernel: the sources whose SHA-256 they are valid for, and the
+# kernel-name substring that selects their dispatches.  One file per kernel and workload.
 TRAFFIC = {
-    "crt_gemm": {"file": os.path.join(ROOT, "profiles", "crt_gemm_traffic.json"),
-                 "sources": [os.path.join(_CSRC, f) for f in ("crt.hip", "crt.hpp", "common.hpp")],
+    "crt_gemm": {"sources": [os.path.join(_CSRC, f) for f in ("crt.hip", "crt.hpp", "common.hpp")],
                  "match": "crt_gemm_kernel"},
-    "gemm_i8": {"file": os.path.join(ROOT, "profiles", "gemm_i8_traffic.json"),
-                "sources": [os.path.join(_CSRC, f) for f in ("gemm_i8.hip", "i8_tile.hpp", "common.hpp")],
+    "gemm_i8": {"sources": [os.path.join(_CSRC, f) for f in ("gemm_i8.hip", "i8_tile.hpp", "common.hpp")],
                 "match": "gemm_i8_kernel"},
 }
+
+
+def traffic_file(kernel, d, L):
+    """The counter summary of `kernel` on the CP-MM of size d over L primes."""
+    name = f"{kernel}_traffic.json" if (d, L) == (8192, 3) else f"{kernel}_traffic_d{d}_L{L}.json"
+    return os.path.join(ROOT, "profiles", name)
 
 
 def kernel_source_hash(kernel: str) -> str:
@@ -88,7 +92,7 @@ def measured_traffic(kernel, d, L):
     """HBM bytes per launch of `kernel` from its committed counter summary, or None when the
     summary is missing, is for another workload, or predates the current kernel source."""
     try:
-        with open(TRAFFIC[kernel]["file"]) as f:
+        with open(traffic_file(kernel, d, L)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -121,7 +125,7 @@ def summarize_counters(fetch_dir, write_dir, d, L, kernel):
            "fetch_kib": fetch, "write_kib": write,
            "fetch_scale": gib_kib / fcopy, "write_scale": gib_kib / wcopy,
            "copy_calibration_kib": {"fetch": fcopy, "write": wcopy, "bytes_copied": 1 << 30}}
-    with open(TRAFFIC[kernel]["file"], "w") as f:
+    with open(traffic_file(kernel, d, L), "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
     return out
@@ -382,8 +386,10 @@ def main():
         per_step = launches / steps
         ops = ops_per_step / per_step
         tops = ops / (ms * 1e-3) / 1e12
+        traffic = measured_traffic(kernel, d, L)
         return {"bound": "mfma", "achieved": tops, "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
-                "frac": tops / INT8_PEAK_TOPS, "traffic": measured_traffic(kernel, d, L),
+                "frac": tops / INT8_PEAK_TOPS, "traffic": traffic,
+                "traffic_gbs": None if traffic is None else traffic / (ms * 1e-3) / 1e9,
                 "kernel": TRAFFIC[kernel]["match"], "avg_launch_ms": ms, "launches": launches,
                 "launches_per_step": per_step, "ops_per_launch": ops, "op": "int8 MAC x 2"}
 
