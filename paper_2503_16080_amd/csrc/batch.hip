@@ -258,14 +258,16 @@ struct CrtBatchLayout {
     CrtScale scale;
     std::vector<CrtSplitJob> sjobs;
     int64_t split_wgs = 0;
-    std::vector<CrtBatchProb> probs;
+    std::vector<CrtItem> items;
+    int n_chunks = 1;
+    int64_t chunk[kMaxChunks + 1] = {0};
     std::vector<CrtSeg> segs;
     std::vector<CrtCombineJob> cjobs;
     int64_t combine_wgs = 0;
     int64_t total_items = 0;
     // descriptor offsets, then the residue planes (offsets relative to off_planes) and the
     // product planes (offsets relative to off_ybytes)
-    size_t off_sjobs = 0, off_probs = 0, off_segs = 0, off_cjobs = 0, off_planes = 0, off_ybytes = 0, bytes = 0;
+    size_t off_sjobs = 0, off_items = 0, off_cjobs = 0, off_planes = 0, off_ybytes = 0, bytes = 0;
 };
 
 hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint64_t *primes, int L,
@@ -325,14 +327,8 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
         lay.split_wgs += lt * kblocks;
         plane_off += (size_t)(lt * kblocks * sub);
 
-        CrtBatchProb bp;
-        std::memset(&bp, 0, sizeof(bp));
-        bp.item_start = lay.total_items;
-        bp.Pd = (const int8_t *)pj.out;
-        bp.Xd = (const int8_t *)(uintptr_t)plane_off;
-        bp.kblocks = (int32_t)kblocks;
-        bp.tiles_m = (int32_t)tiles_m;
-        bp.seg0 = (int32_t)lay.segs.size();
+        const size_t p_off = (size_t)(uintptr_t)pj.out, x_off = plane_off;
+        const size_t seg0 = lay.segs.size();
         int64_t tb = 0;
         for (int l = 0; l < L; ++l) {
             for (int part = 0; part < 2; ++part) {
@@ -391,20 +387,58 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
         }
         plane_off += (size_t)(tb * xsub * kblocks * sub);
         const int64_t items = (int64_t)D * tiles_m * tb;
-        if (items > INT32_MAX / 2 || tb > INT32_MAX / 2) return HLB_EINVAL;
-        bp.tiles_n = (int32_t)tb;
-        bp.nseg = (int32_t)lay.segs.size() - bp.seg0;
+        if (lay.total_items + items > INT32_MAX) return HLB_EINVAL;
+        // the problem's tiles: D moduli as D row bands of a (D tiles_m) x tb grid, walked
+        // group_m row tiles at a time, column by column (neighbours share operand panels);
+        // offsets are rebased once the workspace exists
+        const int64_t tile_stride = kblocks * sub, tm_all = (int64_t)D * tiles_m, group_m = 4;
+        size_t si = seg0;
+        for (int64_t local = 0; local < items; ++local) {
+            const int64_t span = group_m * tb, gi = local / span, first = gi * group_m;
+            const int64_t gm = std::min(group_m, tm_all - first), in = local - gi * span;
+            const int64_t rbv = first + in % gm, cb = in / gm;
+            const int64_t mi = rbv / tiles_m, rb = rbv % tiles_m;
+            si = seg0;
+            while (si + 1 < lay.segs.size() && cb >= lay.segs[si + 1].tile_begin) ++si;
+            const CrtSeg &sg = lay.segs[si];
+            CrtItem it;
+            std::memset(&it, 0, sizeof(it));
+            it.P = (const int8_t *)(uintptr_t)(p_off + (size_t)(2 * rb * tile_stride + mi * 128 * kBK8));
+            it.X = (const int8_t *)(uintptr_t)(x_off + (size_t)(cb * xsub * tile_stride + mi * 128 * kBK8));
+            it.Y = (uint8_t *)(uintptr_t)((uintptr_t)sg.Y + (size_t)(mi * sg.plane));
+            it.nbc = sg.nbc;
+            it.kblocks = (int32_t)kblocks;
+            it.p = kCrtModuli[mi];
+            it.brt = (int32_t)(rb * 8);
+            it.bct = (int32_t)((cb - sg.tile_begin) * (bn / 32));
+            lay.items.push_back(it);
+        }
         lay.total_items += items;
-        lay.probs.push_back(bp);
     }
     if (lay.total_items > INT32_MAX || lay.split_wgs > INT32_MAX || lay.combine_wgs > INT32_MAX) return HLB_EINVAL;
+    // one contiguous run of items per XCD, of about equal cost (an item costs its K blocks
+    // plus about two for its prologue and epilogue)
+    int n_xcd = 8;
+    (void)device_ready(&n_xcd);
+    lay.n_chunks = std::max(1, std::min(n_xcd, kMaxChunks));
+    double total_cost = 0.0;
+    for (const CrtItem &it : lay.items) total_cost += it.kblocks + 2.0;
+    {
+        int c = 1;
+        double acc = 0.0;
+        for (int64_t i = 0; i < (int64_t)lay.items.size() && c < lay.n_chunks; ++i) {
+            acc += lay.items[i].kblocks + 2.0;
+            while (c < lay.n_chunks && acc >= total_cost * c / lay.n_chunks) lay.chunk[c++] = i + 1;
+        }
+        for (; c <= lay.n_chunks; ++c) lay.chunk[c] = lay.total_items;
+        lay.chunk[0] = 0;
+        lay.chunk[lay.n_chunks] = lay.total_items;
+    }
     size_t off = 0;
     lay.off_sjobs = off;
     off = align_up(off + lay.sjobs.size() * sizeof(CrtSplitJob), 256);
-    lay.off_probs = off;
-    off = align_up(off + lay.probs.size() * sizeof(CrtBatchProb), 256);
-    lay.off_segs = off;
-    off = align_up(off + lay.segs.size() * sizeof(CrtSeg), 256);
+    lay.off_items = off;
+    off = align_up(off + lay.items.size() * sizeof(CrtItem), 256);
     lay.off_cjobs = off;
     off = align_up(off + lay.cjobs.size() * sizeof(CrtCombineJob), 256);
     lay.off_planes = off;
@@ -417,27 +451,24 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
 void rebase_crt(CrtBatchLayout &lay, char *base) {
     char *planes = base + lay.off_planes, *ybytes = base + lay.off_ybytes;
     for (CrtSplitJob &j : lay.sjobs) j.out = (int8_t *)(planes + (uintptr_t)j.out);
-    for (CrtBatchProb &p : lay.probs) {
-        p.Pd = (const int8_t *)(planes + (uintptr_t)p.Pd);
-        p.Xd = (const int8_t *)(planes + (uintptr_t)p.Xd);
+    for (CrtItem &it : lay.items) {
+        it.P = (const int8_t *)(planes + (uintptr_t)it.P);
+        it.X = (const int8_t *)(planes + (uintptr_t)it.X);
+        it.Y = (uint8_t *)(ybytes + (uintptr_t)it.Y);
     }
-    for (CrtSeg &sg : lay.segs) sg.Y = (uint8_t *)(ybytes + (uintptr_t)sg.Y);
     for (CrtCombineJob &j : lay.cjobs) j.a.Y = (const uint8_t *)(ybytes + (uintptr_t)j.a.Y);
 }
 
 std::vector<char> crt_descriptor_image(const CrtBatchLayout &lay) {
     std::vector<char> img(lay.off_planes, 0);
     std::memcpy(img.data() + lay.off_sjobs, lay.sjobs.data(), lay.sjobs.size() * sizeof(CrtSplitJob));
-    std::memcpy(img.data() + lay.off_probs, lay.probs.data(), lay.probs.size() * sizeof(CrtBatchProb));
-    std::memcpy(img.data() + lay.off_segs, lay.segs.data(), lay.segs.size() * sizeof(CrtSeg));
+    std::memcpy(img.data() + lay.off_items, lay.items.data(), lay.items.size() * sizeof(CrtItem));
     std::memcpy(img.data() + lay.off_cjobs, lay.cjobs.data(), lay.cjobs.size() * sizeof(CrtCombineJob));
     return img;
 }
 
 // The three launches of a multimodular batch on stream s (capturable: kernels only).
 hlb_status enqueue_crt(const CrtBatchLayout &lay, char *base, hipStream_t s) {
-    int n_xcd = 8;
-    (void)device_ready(&n_xcd);
     {
         ProfScope ps("crt_split_batch", s);
         if (launch_crt_split_batch(lay.D, (const CrtSplitJob *)(base + lay.off_sjobs), (int)lay.sjobs.size(),
@@ -447,13 +478,11 @@ hlb_status enqueue_crt(const CrtBatchLayout &lay, char *base, hipStream_t s) {
     {
         CrtBatchArgs a;
         std::memset(&a, 0, sizeof(a));
-        a.probs = (const CrtBatchProb *)(base + lay.off_probs);
-        a.segs = (const CrtSeg *)(base + lay.off_segs);
+        a.items = (const CrtItem *)(base + lay.off_items);
         a.total_items = lay.total_items;
-        a.nprob = (int32_t)lay.probs.size();
         a.D = lay.D;
-        a.group_m = 4;
-        a.n_xcd = n_xcd;
+        a.n_xcd = lay.n_chunks;
+        for (int c = 0; c <= lay.n_chunks; ++c) a.chunk[c] = lay.chunk[c];
         ProfScope ps("crt_gemm_batch", s);
         if (launch_crt_gemm_batch(a, s) != hipSuccess) return HLB_EDEVICE;
     }

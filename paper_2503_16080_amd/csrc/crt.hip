@@ -20,6 +20,8 @@
 #include "crt.hpp"
 #include "launch.hpp"
 
+#include <algorithm>
+
 namespace hlb {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -332,45 +334,19 @@ __global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_kernel(const CrtGemmAr
                 (int64_t)(cb - sg.tile_begin) * (T::BN / 32));
 }
 
-// A batch of problems in one launch: workgroup w takes work item w (remapped so that each XCD
-// holds a contiguous run of items), finds its problem by binary search over the problems'
-// first items, and its tile within the problem in the raster of crt_gemm_kernel.
+// A batch of problems in one launch.  Workgroups are dealt to the XCDs round-robin, so
+// workgroup w is the (w / n_xcd)-th of XCD w % n_xcd; that XCD serves its run of items in
+// order (neighbouring items share operand panels in its L2), and workgroups past the end of
+// a shorter run exit at once.  The host has resolved every item to its operands, so a
+// workgroup starts with one descriptor load.
 template <class T>
 __global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_batch_kernel(const CrtBatchArgs args) {
     __shared__ __attribute__((aligned(16))) int8_t lds[T::NBUF * T::STAGE];
-    int64_t t = blockIdx.x;
-    if (args.n_xcd > 1) {
-        const int64_t per = args.total_items / args.n_xcd, rem = args.total_items % args.n_xcd;
-        const int64_t x = t % args.n_xcd, local = t / args.n_xcd;
-        t = (x < rem) ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
-    }
-    int lo = 0, hi = args.nprob - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (args.probs[mid].item_start <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    const CrtBatchProb &pb = args.probs[lo];
-    const int local = (int)(t - pb.item_start);
-    const int tm_all = args.D * pb.tiles_m;
-    const int span = args.group_m * pb.tiles_n;
-    const int gi = local / span, first = gi * args.group_m;
-    const int gm = min(args.group_m, tm_all - first);
-    const int in = local - gi * span;
-    const int rbv = first + in % gm, cb = in / gm;
-    const int mi = rbv / pb.tiles_m, rb = rbv % pb.tiles_m;
-    int si = pb.seg0;
-#pragma unroll 1
-    for (int i = pb.seg0 + 1; i < pb.seg0 + pb.nseg; ++i)
-        if (cb >= args.segs[i].tile_begin) si = i;
-    const CrtSeg &sg = args.segs[si];
-    const int KB = pb.kblocks;
-    const int64_t plane_stride = (int64_t)args.D * kCrtSub;
-    const int64_t tile_stride = (int64_t)KB * plane_stride;
-    crt_tile<T>(lds, pb.Pd + (int64_t)(2 * rb) * tile_stride + (int64_t)mi * kCrtSub,
-                pb.Xd + (int64_t)(cb * T::XSUB) * tile_stride + (int64_t)mi * kCrtSub, KB, plane_stride,
-                kCrtModuli[mi], sg.Y + (int64_t)mi * sg.plane, sg.nbc, (int64_t)rb * (kCrtBM / 32),
-                (int64_t)(cb - sg.tile_begin) * (T::BN / 32));
+    const int x = (int)(blockIdx.x % args.n_xcd);
+    const int64_t t = args.chunk[x] + blockIdx.x / args.n_xcd;
+    if (t >= args.chunk[x + 1]) return;
+    const CrtItem it = args.items[t];
+    crt_tile<T>(lds, it.P, it.X, it.kblocks, (int64_t)args.D * kCrtSub, it.p, it.Y, it.nbc, it.brt, it.bct);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -533,8 +509,12 @@ hipError_t launch_crt_split_batch(int D, const CrtSplitJob *jobs, int njobs, int
 
 hipError_t launch_crt_gemm_batch(const CrtBatchArgs &a, hipStream_t s) {
     if (a.total_items <= 0) return hipSuccess;
-    if (a.total_items > INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(crt_gemm_batch_kernel<CrtWide>, dim3((unsigned)a.total_items), dim3(CrtWide::THREADS), 0, s, a);
+    if (a.n_xcd < 1 || a.n_xcd > kMaxChunks || a.total_items > INT32_MAX) return hipErrorInvalidValue;
+    int64_t longest = 0;
+    for (int x = 0; x < a.n_xcd; ++x) longest = std::max<int64_t>(longest, a.chunk[x + 1] - a.chunk[x]);
+    const int64_t grid = longest * a.n_xcd;
+    if (grid > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(crt_gemm_batch_kernel<CrtWide>, dim3((unsigned)grid), dim3(CrtWide::THREADS), 0, s, a);
     return hipGetLastError();
 }
 

@@ -105,22 +105,24 @@ struct CrtSplitJob {
     int8_t *out;
 };
 
-// A problem of a multimodular batch: its plane workspaces, its GEMM tiles (D * tiles_m row
-// bands x tiles_n column tiles, items [item_start, item_start + D tiles_m tiles_n)) and its
-// output segments seg0 .. seg0 + nseg - 1 (right operands in order; their planes follow
-// one another from Xd).
-struct CrtBatchProb {
-    int64_t item_start;
-    const int8_t *Pd;
-    const int8_t *Xd;
-    int32_t kblocks, tiles_m, tiles_n, seg0, nseg, pad;
+// One GEMM tile of a multimodular batch, resolved on the host: the first plane blocks of its
+// left and right operands for its modulus (k block 0), its k blocks, the modulus, and the
+// product plane it writes (block-row and block-column bases, blocks per plane row).
+struct CrtItem {
+    const int8_t *P;
+    const int8_t *X;
+    uint8_t *Y;
+    int64_t nbc;
+    int32_t kblocks, p, brt, bct;
 };
 
+// The items are cut into n_xcd contiguous runs of about equal cost (items differ in K), run x
+// being [chunk[x], chunk[x + 1]); XCD x serves run x.
 struct CrtBatchArgs {
-    const CrtBatchProb *probs;
-    const CrtSeg *segs;
+    const CrtItem *items;
     int64_t total_items;
-    int32_t nprob, D, group_m, n_xcd;
+    int32_t D, n_xcd;
+    int64_t chunk[kMaxChunks + 1];
 };
 
 // A recombination job of a batch: the output matrix's arguments and its first workgroup.
