@@ -212,3 +212,24 @@ def test_batch_multimodular_replays_and_degenerate_members(graph):
                 assert np.array_equal(_np(pr["PA"]), wA) and np.array_equal(_np(pr["PB"]), wB)
     finally:
         hlb.set_option(hlb.OPT_BATCH_GRAPH, 1)
+
+
+def test_batch_multimodular_moduli_count_from_largest_member():
+    # one member with a 40-bit plaintext sets the batch's moduli count (14 instead of 10);
+    # every member, also the 20-bit ones, must stay exact with it
+    primes = wl.ntt_primes(50, 2, skip=4)
+    g = wl.rng(5900)
+    shapes = [(100, 300, 70, 130, 20), (257, 64, 300, 33, 40), (64, 129, 64, 64, 20)]
+    assert hlb.plan(1, 300, max(primes), 1 << 40, "int8_crt")["p_limbs"] == 14
+    probs, want = [], []
+    for m, k, nA, nB, bits in shapes:
+        P = wl.plaintext_matrix(g, m, k, scale_bits=bits)
+        A = np.stack([wl.uniform_residues(g, (k, nA), q) for q in primes])
+        B = np.stack([wl.uniform_residues(g, (k, nB), q) for q in primes])
+        probs.append(dict(P=_t(P), A=_t(A), B=_t(B), p_absmax=1 << bits,
+                          PA=torch.empty((2, m, nA), dtype=torch.int64, device=DEV),
+                          PB=torch.empty((2, m, nB), dtype=torch.int64, device=DEV)))
+        want.append(oracle.cp_mm(P, A, B, primes))
+    hlb.cp_mm_batch(probs, primes, form="int8_crt")
+    for p, (wA, wB) in zip(probs, want):
+        assert np.array_equal(_np(p["PA"]), wA) and np.array_equal(_np(p["PB"]), wB)
