@@ -31,6 +31,7 @@ static std::atomic<int> g_batch_graph{1};
 static std::atomic<int> g_force_class{-1};
 static std::atomic<int> g_f64_planes{1};
 static std::atomic<int> g_crt_wide{1};
+static std::atomic<int64_t> g_ws_cap{0};
 
 int64_t opt_force_kchunk() { return g_force_kchunk.load(); }
 bool opt_batch_graph() { return g_batch_graph.load() != 0; }
@@ -402,6 +403,8 @@ static size_t ws_bucket(size_t bytes) {
 hlb_status ws_alloc(void **p, size_t bytes, hipStream_t s) {
     *p = nullptr;
     if (bytes == 0) return HLB_OK;
+    const int64_t cap = g_ws_cap.load();
+    if (cap > 0 && ws_bucket(bytes) > (size_t)cap) return HLB_ENOMEM;
     if (hipMallocAsync(p, ws_bucket(bytes), s) != hipSuccess) {
         (void)hipGetLastError();
         return HLB_ENOMEM;
@@ -1050,6 +1053,10 @@ hlb_status hlb_set_option(int option, int64_t value) {
             return HLB_OK;
         case HLB_OPT_CRT_WIDE:
             g_crt_wide.store(value ? 1 : 0);
+            return HLB_OK;
+        case HLB_OPT_WS_CAP:
+            if (value < 0) return HLB_EINVAL;
+            g_ws_cap.store(value);
             return HLB_OK;
         default: return HLB_EUNSUP;
     }

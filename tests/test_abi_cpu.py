@@ -144,6 +144,8 @@ def test_entry_points_reject_bad_arguments_before_device_work():
     assert lib.hlb_set_option(hlb.OPT_FORCE_KCHUNK, -5) == 1
     for opt in (hlb.OPT_CRT_WIDE, hlb.OPT_F64_PLANES):
         assert lib.hlb_set_option(opt, 0) == 0 and lib.hlb_set_option(opt, 1) == 0
+    assert lib.hlb_set_option(hlb.OPT_WS_CAP, -1) == 1
+    assert lib.hlb_set_option(hlb.OPT_WS_CAP, 1 << 20) == 0 and lib.hlb_set_option(hlb.OPT_WS_CAP, 0) == 0
 
 
 def test_no_silent_fallback_without_library(monkeypatch):

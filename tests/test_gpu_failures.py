@@ -1,0 +1,75 @@
+"""GPU failure paths forced from the host: a workspace cap makes every form's allocation
+fail with HLB_ENOMEM before any kernel touches the outputs, and the next uncapped call is
+exact again (against the oracle)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2503_16080_amd as hlb
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+ENOMEM = 4
+
+
+def _t(a):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    return torch.from_numpy(a).to(DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("form", ["int8_crt", "int8", "fp64"])
+def test_workspace_cap_fails_cleanly_then_recovers(form):
+    w = wl.cpmm_uniform(6100, 512, 512, 512, 50, 2)
+    P, A, B = _t(w.P), _t(w.A), _t(w.B)
+    PA = torch.full((2, 512, 512), -1, dtype=torch.int64, device=DEV)
+    PB = torch.full((2, 512, 512), -1, dtype=torch.int64, device=DEV)
+    try:
+        hlb.set_option(hlb.OPT_WS_CAP, 1 << 20)
+        with pytest.raises(hlb.HlbError) as err:
+            hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form=form, out=(PA, PB))
+        assert err.value.status == ENOMEM
+        assert bool((PA == -1).all()) and bool((PB == -1).all())
+    finally:
+        hlb.set_option(hlb.OPT_WS_CAP, 0)
+    hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form=form, out=(PA, PB))
+    wantA, wantB = oracle.cp_mm(w.P, w.A, w.B, w.primes)
+    assert np.array_equal(_np(PA), wantA) and np.array_equal(_np(PB), wantB)
+
+
+@pytest.mark.parametrize("form", ["int8", "int8_crt"])
+def test_eager_batch_workspace_cap(form):
+    primes = wl.ntt_primes(45, 2)
+    g = wl.rng(6200)
+    probs, want = [], []
+    for m, k, n in ((300, 400, 260), (130, 257, 500)):
+        P = wl.plaintext_matrix(g, m, k)
+        A = np.stack([wl.uniform_residues(g, (k, n), q) for q in primes])
+        B = np.stack([wl.uniform_residues(g, (k, n), q) for q in primes])
+        probs.append(dict(P=_t(P), A=_t(A), B=_t(B), p_absmax=1 << 20,
+                          PA=torch.full((2, m, n), -1, dtype=torch.int64, device=DEV),
+                          PB=torch.full((2, m, n), -1, dtype=torch.int64, device=DEV)))
+        want.append(oracle.cp_mm(P, A, B, primes))
+    hlb.set_option(hlb.OPT_BATCH_GRAPH, 0)
+    try:
+        hlb.set_option(hlb.OPT_WS_CAP, 1 << 20)
+        with pytest.raises(hlb.HlbError) as err:
+            hlb.cp_mm_batch(probs, primes, form=form)
+        assert err.value.status == ENOMEM
+        for p in probs:
+            assert bool((p["PA"] == -1).all()) and bool((p["PB"] == -1).all())
+        hlb.set_option(hlb.OPT_WS_CAP, 0)
+        hlb.cp_mm_batch(probs, primes, form=form)
+    finally:
+        hlb.set_option(hlb.OPT_WS_CAP, 0)
+        hlb.set_option(hlb.OPT_BATCH_GRAPH, 1)
+    for p, (wA, wB) in zip(probs, want):
+        assert np.array_equal(_np(p["PA"]), wA) and np.array_equal(_np(p["PB"]), wB)
