@@ -37,20 +37,31 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // ---------------------------------------------------------------------------------------
 constexpr int kCrtR = 128;  // rows (columns) per split tile
 
+// The low bytes of four words as one word (three byte permutes).
+__device__ __forceinline__ uint32_t crt_pack4(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3) {
+    const uint32_t lo = __builtin_amdgcn_perm(b1, b0, 0x0c0c0400u);  // b0, b1, 0, 0
+    const uint32_t hi = __builtin_amdgcn_perm(b3, b2, 0x0c0c0400u);  // b2, b3, 0, 0
+    return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+}
+
 template <int I, int D, bool SCALED>
-__device__ __forceinline__ void crt_store_planes(const CrtPieces (&x)[16], int8_t *dst, const CrtScale &scale) {
+__device__ __forceinline__ void crt_store_planes(const CrtValue (&x)[16], int8_t *dst, const CrtScale &scale) {
     if constexpr (I < D) {
+        constexpr int p = kCrtModuli[I];
         uint32_t w[4];
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
-            uint32_t v = 0;
+            uint32_t b[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                int b = crt_residue<I>(x[q4 * 4 + e]);
-                if constexpr (SCALED) b = crt_balanced(__mul24(b, scale.s[I]), kCrtModuli[I], 1.0f / (float)kCrtModuli[I]);
-                v |= ((uint32_t)b & 0xffu) << (8 * e);
+                b[e] = crt_residue_word<p>(x[q4 * 4 + e]);
+                // the residue r itself, to scale: for p < 256 the word holds r modulo 2^24 and
+                // |r| < 2^7, so its low 24 bits, which the 24-bit multiply reads as a signed
+                // number, are r; for p = 256 its byte
+                if constexpr (SCALED)
+                    b[e] = crt_small_residue_word<p>(p == 256 ? (int)(int8_t)b[e] * scale.s[I] : __mul24((int)b[e], scale.s[I]));
             }
-            w[q4] = v;
+            w[q4] = crt_pack4(b[0], b[1], b[2], b[3]);
         }
         *(uint4 *)(dst + I * kCrtR * 64) = uint4{w[0], w[1], w[2], w[3]};
         crt_store_planes<I + 1, D, SCALED>(x, dst, scale);
@@ -58,12 +69,12 @@ __device__ __forceinline__ void crt_store_planes(const CrtPieces (&x)[16], int8_
 }
 
 // blk: the [D][128][64] block of this (tile, k block); row r, logical chunk c.  With SCALED,
-// each residue b becomes the balanced residue of b * s_i (|b s_i| < 2^15).
+// each residue b becomes the residue of b * s_i (|b s_i| < 2^15).
 template <int D, bool SCALED>
 __device__ __forceinline__ void crt_store_chunk(const int64_t (&v)[16], int8_t *blk, int r, int c, const CrtScale scale) {
-    CrtPieces x[16];
+    CrtValue x[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) x[e] = crt_pieces(v[e]);
+    for (int e = 0; e < 16; ++e) x[e] = crt_value(v[e]);
     crt_store_planes<0, D, SCALED>(x, blk + r * 64 + ((c ^ swz(r)) << 4), scale);
 }
 

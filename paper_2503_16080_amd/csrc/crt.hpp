@@ -18,37 +18,42 @@ constexpr int kCrtMaxModuli = 16;
 constexpr int kCrtModuli[kCrtMaxModuli] = {256, 255, 253, 251, 247, 241, 239, 233,
                                            229, 227, 223, 211, 199, 197, 193, 191};
 
-constexpr int crt_pow2_mod(int e, int p) {
-    int r = 1 % p;
-    for (int i = 0; i < e; ++i) r = (2 * r) % p;
-    return r;
-}
-
-// A signed integer |s| < 2^52 as s = a 2^32 + b 2^16 + c with |a| <= 2^20, 0 <= b, c < 2^16.
-struct CrtPieces {
-    int a, b, c;
+// A signed integer |s| < 2^52, held as the exact double sd and its low word lo.
+struct CrtValue {
+    double sd;
+    uint32_t lo;
 };
-__device__ __forceinline__ CrtPieces crt_pieces(int64_t s) {
-    return {(int)(s >> 32), (int)(((uint64_t)s >> 16) & 0xffffu), (int)((uint64_t)s & 0xffffu)};
+__device__ __forceinline__ CrtValue crt_value(int64_t s) {
+    const double hi = (double)(int32_t)(s >> 32);
+    return {__builtin_fma(hi, 4294967296.0, (double)(uint32_t)s), (uint32_t)s};
 }
 
-// Balanced residue of an integer |u| < 2^29 modulo p <= 256, in [-(p/2), (p-1)/2]: the
-// nearest-integer quotient estimate from single precision is off by at most one (|u| / p
-// carries an error below 0.3), and one correction each way removes that.
-__device__ __forceinline__ int crt_balanced(int u, int p, float pinv) {
-    const int t = (int)__builtin_floorf(__builtin_fmaf((float)u, pinv, 0.5f));
-    int r = u - __mul24(t, p);
-    r = r > (p - 1) / 2 ? r - p : r;
-    return r < -(p / 2) ? r + p : r;
+// A word whose low byte is the int8 residue of s modulo p (the balanced residue; for p = 256
+// the byte of s itself, where +128 and -128 coincide modulo 256).
+//  * t = the nearest integer to s / p: s (1/p) + 1.5 2^52 lies in [2^52, 2^53), where doubles
+//    are spaced by 1, so one fused multiply-add rounds it to 1.5 2^52 + t, whose low word is
+//    t mod 2^32.  The double 1/p is within 2^-53 relative of 1/p, so s (1/p) is within
+//    |s| 2^-53 / p < 1 / (2p) of s / p, while for odd p s / p lies at least 1 / (2p) from any
+//    half-integer: the rounding is that of s / p itself.  For p = 256, 1/p is exact.
+//  * s - t p, of magnitude at most p / 2, is then formed modulo 2^24 by one 24-bit
+//    multiply-add with 2^24 - p, and its low byte is the residue.
+template <int P>
+__device__ __forceinline__ uint32_t crt_residue_word(const CrtValue &v) {
+    if constexpr (P == 256) {
+        return v.lo;
+    } else {
+        const double td = __builtin_fma(v.sd, 1.0 / (double)P, 6755399441055744.0);
+        const uint32_t t = (uint32_t)__double2loint(td);
+        return __umul24(t, (1u << 24) - (uint32_t)P) + v.lo;
+    }
 }
 
-// Balanced residue of the pieces modulo the i-th modulus: a (2^32 mod p) + b (2^16 mod p) + c
-// is congruent to s and below 2^28.1 in magnitude.
-template <int I>
-__device__ __forceinline__ int crt_residue(const CrtPieces &x) {
-    constexpr int p = kCrtModuli[I];
-    constexpr int e32 = crt_pow2_mod(32, p), e16 = crt_pow2_mod(16, p);
-    return crt_balanced(__mul24(x.a, e32) + __mul24(x.b, e16) + x.c, p, 1.0f / (float)p);
+// The same in single precision for |x| < 2^23 (a residue times a factor): x (1/p) + 1.5 2^23
+// is rounded to 1.5 2^23 + t, whose low 24 bits hold 2^22 + t, and 2^22 p vanishes modulo 2^8.
+template <int P>
+__device__ __forceinline__ uint32_t crt_small_residue_word(int x) {
+    const float tf = __builtin_fmaf((float)x, 1.0f / (float)P, 12582912.0f);
+    return __umul24(__float_as_uint(tf), (1u << 24) - (uint32_t)P) + (uint32_t)x;
 }
 
 // Product planes.  The GEMM of modulus i writes y_i = C_i mod p_i as one byte per entry (the
