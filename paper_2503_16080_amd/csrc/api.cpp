@@ -597,9 +597,7 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
     if (k == 0) {
         for (const LeftSpec &L : lefts)
             for (size_t r = 0; r < rights.size(); ++r)
-                if (L.m > 0 && rights[r].n > 0 &&
-                    hipMemset2DAsync(L.C[r], L.ldc[r] * 8, 0, rights[r].n * 8, L.m, s) != hipSuccess)
-                    return HLB_EDEVICE;
+                if (launch_zero(L.C[r], L.m, rights[r].n, L.ldc[r], s) != hipSuccess) return HLB_EDEVICE;
         return HLB_OK;
     }
     if (pl.form == HLB_FORM_INT8_CRT) return run_products_crt(pl, lefts, rights, k, n_xcd, s);

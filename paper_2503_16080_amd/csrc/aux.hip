@@ -1,5 +1,5 @@
-// aux.hip -- small elementwise / reduction kernels: residue validation, plaintext bound,
-// and the test-only CKKS helpers (coefficient encoding, encryption/decryption combine).
+// aux.hip -- small elementwise / reduction kernels: residue validation, plaintext bound, zero
+// fill, and the test-only CKKS helpers (coefficient encoding, encryption/decryption combine).
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -47,6 +47,17 @@ __global__ void absmax_kernel(const int64_t *__restrict__ P, int64_t m, int64_t 
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicMax(out, red[0]);
+}
+
+// Zeros in a rows x cols block of 64-bit words (row stride ld): the outputs of a product over
+// k = 0.  A kernel rather than a memset, so that a caller may capture the call in a graph.
+__global__ void zero_kernel(uint64_t *__restrict__ C, int64_t rows, int64_t cols, int64_t ld) {
+    const int64_t total = rows * cols;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / cols, c = i - r * cols;
+        C[r * ld + c] = 0;
+    }
 }
 
 // The paper's rounding floor(x + 1/2) of delta * M (Section 2 notation; coefficient encoding).
@@ -117,6 +128,12 @@ hipError_t launch_validate(const uint64_t *X, int64_t rows, int64_t cols, int64_
 hipError_t launch_absmax(const int64_t *P, int64_t m, int64_t k, int64_t ld, unsigned long long *out,
                          hipStream_t s) {
     hipLaunchKernelGGL(absmax_kernel, dim3(aux_grid(m * k)), dim3(kAuxThreads), 0, s, P, m, k, ld, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(uint64_t *C, int64_t rows, int64_t cols, int64_t ld, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_kernel, dim3(aux_grid(rows * cols)), dim3(kAuxThreads), 0, s, C, rows, cols, ld);
     return hipGetLastError();
 }
 

@@ -691,9 +691,8 @@ extern "C" hlb_status hlb_cp_mm_batch(const hlb_cpmm_problem *probs, int count, 
     for (const hlb_cpmm_problem &p : local) {
         if (p.k != 0 || p.m == 0) continue;
         for (int l = 0; l < L; ++l) {
-            if (p.nA > 0 && hipMemsetAsync(p.PA + (int64_t)l * p.m * p.nA, 0, (size_t)(p.m * p.nA * 8), s) != hipSuccess)
-                return HLB_EDEVICE;
-            if (p.nB > 0 && hipMemsetAsync(p.PB + (int64_t)l * p.m * p.nB, 0, (size_t)(p.m * p.nB * 8), s) != hipSuccess)
+            if (launch_zero(p.PA + (int64_t)l * p.m * p.nA, p.m, p.nA, p.nA, s) != hipSuccess ||
+                launch_zero(p.PB + (int64_t)l * p.m * p.nB, p.m, p.nB, p.nB, s) != hipSuccess)
                 return HLB_EDEVICE;
         }
     }

@@ -188,6 +188,12 @@ def test_edge_shapes():
     for form in FORMS:
         hlb.mod_pp_mm(q, P, X, form=form, out=C)
         assert (_np(C) == 0).all()
+    # ... only inside a strided output: the columns around it keep their values
+    for form in FORMS:
+        big = torch.full((5, 9), 7, dtype=torch.int64, device=DEV)
+        hlb.mod_pp_mm(q, P, X, form=form, out=big[:, 1:7])
+        b = _np(big)
+        assert (b[:, 1:7] == 0).all() and (b[:, 0] == 7).all() and (b[:, 7:] == 7).all()
     A = torch.zeros((1, 0, 6), dtype=torch.int64, device=DEV)
     PA, PB = hlb.cp_mm(P, A, A, primes, p_absmax=1, form="int8")
     assert (_np(PA) == 0).all() and (_np(PB) == 0).all()
