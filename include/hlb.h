@@ -245,8 +245,9 @@ typedef enum {
                                  operands into double planes (library workspace), then the
                                  direct-to-LDS GEMM; 0 = the register-staged kernel, which
                                  needs no workspace.  Results are identical. */
-    HLB_OPT_CRT_WIDE = 6,     /* multimodular GEMM tile: 1 (default) = 256 x 256 outputs,
-                                 0 = 256 x 128.  Results are identical. */
+    HLB_OPT_CRT_WIDE = 6,     /* multimodular GEMM tile: 2 (default) = 256 x 384 outputs,
+                                 1 = 256 x 256, 0 = 256 x 128; other values are refused with
+                                 HLB_EINVAL.  Results are identical. */
     HLB_OPT_WS_CAP = 7        /* > 0: refuse any single stream-ordered workspace allocation
                                  above this many bytes with HLB_ENOMEM, before any launch
                                  that would use it (a host-side way to exercise the

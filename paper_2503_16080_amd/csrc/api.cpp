@@ -30,7 +30,7 @@ static std::atomic<int> g_profile{0};
 static std::atomic<int> g_batch_graph{1};
 static std::atomic<int> g_force_class{-1};
 static std::atomic<int> g_f64_planes{1};
-static std::atomic<int> g_crt_wide{1};
+static std::atomic<int> g_crt_wide{2};
 static std::atomic<int64_t> g_ws_cap{0};
 
 int64_t opt_force_kchunk() { return g_force_kchunk.load(); }
@@ -431,18 +431,19 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
     int64_t mmax = 0;
     for (const LeftSpec &L : lefts) mmax = std::max(mmax, L.m);
     const int64_t t128_m = ((mmax + 255) / 256) * 2;  // 128-row tiles, even: GEMM tiles are 256 rows
-    // per right operand: GEMM column tiles, and the 128-column split tiles that back them
-    std::vector<int64_t> tg_n(rights.size()), t128_n(rights.size());
+    // per right operand: its 128-column split tiles.  The right operands of one GEMM launch lie
+    // side by side, and its GEMM tiles (xsub split tiles wide) may straddle two of them; the
+    // last may reach up to xsub - 1 split tiles past the end, so the workspace has them too.
+    std::vector<int64_t> t128_n(rights.size());
     int64_t tn_total = 0, ybytes = 0;
     for (size_t i = 0; i < rights.size(); ++i) {
-        tg_n[i] = (rights[i].n + bn - 1) / bn;
-        t128_n[i] = tg_n[i] * xsub;
+        t128_n[i] = (rights[i].n + 127) / 128;
         tn_total += t128_n[i];
-        // product planes cover whole GEMM tiles (layout of CrtSeg)
-        ybytes += (int64_t)D * (t128_m / 2 * 256) * (tg_n[i] * bn);
+        // product planes cover whole 256-row and 128-column tiles (layout of CrtSeg)
+        ybytes += (int64_t)D * (t128_m / 2 * 256) * (t128_n[i] * 128);
     }
-    if (kblocks > INT32_MAX / 2 || t128_m * kblocks > INT32_MAX / 2 || tn_total * kblocks > INT32_MAX / 2 ||
-        (int64_t)D * (t128_m / 2) * tn_total > INT32_MAX / 2)
+    if (kblocks > INT32_MAX / 2 || t128_m * kblocks > INT32_MAX / 2 || (tn_total + xsub) * kblocks > INT32_MAX / 2 ||
+        (int64_t)D * (t128_m / 2) * (tn_total + xsub) > INT32_MAX / 2)
         return HLB_EINVAL;
 
     // constants: M = prod p_i, inv_i = (M / p_i)^{-1} mod p_i
@@ -467,7 +468,7 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
         ws_free(wsY, s);
     };
     hlb_status st = ws_alloc(&wsP, (size_t)(t128_m * kblocks * sub), s);
-    if (st == HLB_OK) st = ws_alloc(&wsX, (size_t)(tn_total * kblocks * sub), s);
+    if (st == HLB_OK) st = ws_alloc(&wsX, (size_t)((tn_total + xsub - 1) * kblocks * sub), s);
     if (st == HLB_OK) st = ws_alloc(&wsY, (size_t)ybytes, s);
     if (st != HLB_OK) {
         release();
@@ -481,7 +482,7 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
             x_tile0[i] = t0;
             y_off[i] = y0;
             t0 += t128_n[i];
-            y0 += (int64_t)D * (t128_m / 2 * 256) * (tg_n[i] * bn);
+            y0 += (int64_t)D * (t128_m / 2 * 256) * (t128_n[i] * 128);
         }
     }
     auto split_x = [&](size_t i, hipStream_t st) -> bool {
@@ -504,8 +505,9 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
         const int64_t lt = ((L.m + 255) / 256) * 2;
         sg.Y = (uint8_t *)wsY + y_off[i];
         sg.n = rights[i].n;
-        sg.nbc = tg_n[i] * bn / 32;
-        sg.plane = (lt / 2 * 256) * (tg_n[i] * bn);
+        sg.nbc = t128_n[i] * 4;
+        sg.plane = (lt / 2 * 256) * (t128_n[i] * 128);
+        sg.tiles = (int32_t)t128_n[i];
         return sg;
     };
     // one GEMM launch for right operands [first, last), all D moduli
@@ -525,9 +527,9 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
             CrtSeg &sg = a.seg[a.nseg++];
             sg = segment(L, i);
             sg.tile_begin = tb;
-            tb += (int32_t)tg_n[i];
+            tb += (int32_t)t128_n[i];
         }
-        a.tiles_n = tb;
+        a.tiles_n = (int32_t)((tb + xsub - 1) / xsub);
         if (tb == 0) return true;
         ProfScope ps("crt_gemm", st);
         return launch_crt_gemm(wide, a, st) == hipSuccess;
@@ -1050,7 +1052,8 @@ hlb_status hlb_set_option(int option, int64_t value) {
             g_f64_planes.store(value ? 1 : 0);
             return HLB_OK;
         case HLB_OPT_CRT_WIDE:
-            g_crt_wide.store(value ? 1 : 0);
+            if (value < 0 || value > 2) return HLB_EINVAL;
+            g_crt_wide.store((int)value);
             return HLB_OK;
         case HLB_OPT_WS_CAP:
             if (value < 0) return HLB_EINVAL;

@@ -357,7 +357,8 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
                 sg.n = n;
                 sg.nbc = tg * bn / 32;
                 sg.plane = (tiles_m * 256) * (tg * bn);
-                sg.tile_begin = (int32_t)tb;
+                sg.tile_begin = (int32_t)(tb * xsub);
+                sg.tiles = (int32_t)(tg * xsub);
                 lay.segs.push_back(sg);
 
                 CrtCombineJob cj;
@@ -399,7 +400,7 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
             const int64_t rbv = first + in % gm, cb = in / gm;
             const int64_t mi = rbv / tiles_m, rb = rbv % tiles_m;
             si = seg0;
-            while (si + 1 < lay.segs.size() && cb >= lay.segs[si + 1].tile_begin) ++si;
+            while (si + 1 < lay.segs.size() && cb * xsub >= lay.segs[si + 1].tile_begin) ++si;
             const CrtSeg &sg = lay.segs[si];
             CrtItem it;
             std::memset(&it, 0, sizeof(it));
@@ -410,7 +411,7 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
             it.kblocks = (int32_t)kblocks;
             it.p = kCrtModuli[mi];
             it.brt = (int32_t)(rb * 8);
-            it.bct = (int32_t)((cb - sg.tile_begin) * (bn / 32));
+            it.bct = (int32_t)((cb * xsub - sg.tile_begin) * 4);
             lay.items.push_back(it);
         }
         lay.total_items += items;

@@ -167,9 +167,11 @@ __global__ __launch_bounds__(512) void crt_split_batch(const CrtSplitJob *__rest
 // ---------------------------------------------------------------------------------------
 // 2. One INT8 product per modulus on a 256 x BN output tile: WM x WN waves, each owning
 //    MB x NB blocks of 32 x 32 outputs (WM * MB * 32 = 256).  Variants (tile, waves, block
-//    per wave): 256 x 128 with 8 waves of 64 x 64; 256 x 256 with 8 waves of 64 x 128.
-//    (Four waves of 128 x 128 need their 256 accumulators in AGPRs and leave one wave per
-//    SIMD, which hides less latency: measured slower.)
+//    per wave): 256 x 128 with 8 waves of 64 x 64; 256 x 256 with 8 waves of 64 x 128;
+//    256 x 384 with 8 waves of 128 x 96 (the default: 24 MFMAs per wave and stage, the most
+//    that two waves per SIMD can hold accumulators for, with 12% fewer LDS bytes per MFMA than
+//    64 x 128).  (Four waves of 128 x 128 need their 256 accumulators in AGPRs and leave one
+//    wave per SIMD, which hides less latency: measured slower.)
 // ---------------------------------------------------------------------------------------
 constexpr int kCrtBM = 256;
 constexpr int kCrtSub = kCrtR * kBK8;  // bytes of one plane block (128 x 64)
@@ -189,6 +191,7 @@ struct CrtTile {
 };
 using CrtNarrow = CrtTile<2, 2, 4, 2>;
 using CrtWide = CrtTile<2, 4, 4, 2>;
+using CrtWider = CrtTile<4, 3, 2, 4>;
 
 // c mod p in [0, p) for any int32 c and p <= 256: with c = h 2^16 + l (h signed, 0 <= l <
 // 2^16), u = h (2^16 mod p) + l satisfies |u| < 2^24, so u and the quotient estimate
@@ -203,12 +206,20 @@ __device__ __forceinline__ uint32_t crt_y(int c, int p, int c16, float pinv) {
     return (uint32_t)r;
 }
 
+// Where the 32-column block column bc of a tile goes: the product-plane block of its first
+// block row (1 KiB per 32 x 32 block) and the bytes from one block row to the next; null p
+// for a column outside every output.
+struct CrtBlockCol {
+    uint8_t *p;
+    int64_t row_bytes;
+};
+
 // One 256 x BN output tile of one modulus: the K loop over the plane blocks at gP (left, two
-// 128-row blocks tile_stride apart) and gX (right, XSUB 128-column blocks), then the epilogue
-// into the modulus' product plane Y (block rows from brt, block columns from bct).
-template <class T>
+// 128-row blocks tile_stride apart) and gX (right, XSUB 128-column blocks), then the epilogue,
+// which stores block column bc at dst(bc) (a wave-uniform CrtBlockCol).
+template <class T, class Dst>
 __device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const int8_t *gX, int KB, int64_t plane_stride,
-                                         int p, uint8_t *Y, int64_t nbc, int64_t brt, int64_t bct) {
+                                         int p, const Dst &dst) {
     constexpr int MB = T::MB, NB = T::NB, kCrtThreads = T::THREADS, kCrtWavesN = T::WN;
     constexpr int kCrtNbuf = T::NBUF;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -280,6 +291,33 @@ __device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const in
         if (st < KB) gload(st, st);
     wait_vmcnt(outstanding(G - 1, kCrtNbuf - 1));
     stage_barrier();
+    if constexpr (MB * NB >= 12) {
+        // 192 accumulator registers leave room for one half-stage of fragments: each half
+        // reads its own, and the other wave on the SIMD covers the wait
+#pragma unroll 1
+        for (int kb = 0; kb < KB; kb += G) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int st = kb + g;
+                if (st >= KB) break;
+                const int cur = st % kCrtNbuf;
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) {
+                    Frags f;
+                    read_frags(f, cur, kk);
+                    mfmas(f);
+                }
+                if (g == G - 1 || st + 1 == KB) {
+                    wait_lds_after_mfmas();
+                    wait_vmcnt(outstanding(kb + 2 * G - 1, kb + kCrtNbuf - 1));
+                    stage_barrier();
+#pragma unroll
+                    for (int h = 0; h < G; ++h)
+                        if (kb + h + kCrtNbuf < KB) gload(kb + h + kCrtNbuf, (kb + h) % kCrtNbuf);
+                }
+            }
+        }
+    } else {
     Frags f0, f1;
     read_frags(f0, 0, 0);
 #pragma unroll 1
@@ -305,24 +343,28 @@ __device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const in
             mfmas(f1);
         }
     }
+    }
 
-    // epilogue: one 16-byte store per 32 x 32 block and lane (the plane covers whole tiles)
+    // epilogue: one 16-byte store per 32 x 32 block and lane
     const int c16 = (1 << 16) % p;
     const float pinv = 1.0f / (float)p;
-    const int64_t br0 = brt + wm * MB;
-    const int64_t bc0 = bct + wn * NB;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+    for (int nb = 0; nb < NB; ++nb) {
+        const CrtBlockCol col = dst(wn * NB + nb);
+        if (!col.p) continue;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
+        for (int mb = 0; mb < MB; ++mb) {
             uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
             for (int r = 0; r < 16; ++r) w[r >> 2] |= crt_y(acc[mb][nb][r], p, c16, pinv) << (8 * (r & 3));
-            const int64_t blk = (br0 + mb) * nbc + bc0 + nb;
-            *(uint4 *)(Y + (blk * 64 + lane) * 16) = uint4{w[0], w[1], w[2], w[3]};
+            *(uint4 *)(col.p + (wm * MB + mb) * col.row_bytes + lane * 16) = uint4{w[0], w[1], w[2], w[3]};
         }
+    }
 }
 
+// The output matrices of a launch lie side by side in 128-column plane tiles, so a GEMM tile
+// may straddle two of them (and the last may run past the end): each 32-column block of the
+// tile finds its matrix, and blocks past the last one are not stored.
 template <class T>
 __global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_kernel(const CrtGemmArgs args) {
     __shared__ __attribute__((aligned(16))) int8_t lds[T::NBUF * T::STAGE];
@@ -331,18 +373,24 @@ __global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_kernel(const CrtGemmAr
     int rbv, cb;
     map_tile(blockIdx.x, total, args.n_xcd, args.D * args.tiles_m, args.tiles_n, args.group_m, rbv, cb);
     const int mi = rbv / args.tiles_m, rb = rbv % args.tiles_m;
-    int si = 0;
-#pragma unroll 1
-    for (int i = 1; i < args.nseg; ++i)
-        if (cb >= args.seg[i].tile_begin) si = i;
-    const CrtSeg &sg = args.seg[si];
     const int KB = args.kblocks;
     const int64_t plane_stride = (int64_t)args.D * kCrtSub;  // bytes of one k block of a 128-wide tile
     const int64_t tile_stride = (int64_t)KB * plane_stride;
+    const int64_t pt0 = (int64_t)cb * T::XSUB;  // first plane tile of this GEMM tile
+    auto dst = [&](int bc) -> CrtBlockCol {
+        const int64_t pt = pt0 + bc / 4;
+#pragma unroll 1
+        for (int i = 0; i < args.nseg; ++i) {
+            const CrtSeg &sg = args.seg[i];
+            if (pt >= sg.tile_begin && pt < sg.tile_begin + sg.tiles)
+                return {sg.Y + (int64_t)mi * sg.plane +
+                            ((int64_t)rb * (kCrtBM / 32) * sg.nbc + (pt - sg.tile_begin) * 4 + bc % 4) * 1024,
+                        sg.nbc * 1024};
+        }
+        return {nullptr, 0};
+    };
     crt_tile<T>(lds, args.Pd + (int64_t)(2 * rb) * tile_stride + (int64_t)mi * kCrtSub,
-                args.Xd + (int64_t)(cb * T::XSUB) * tile_stride + (int64_t)mi * kCrtSub, KB, plane_stride,
-                kCrtModuli[mi], sg.Y + (int64_t)mi * sg.plane, sg.nbc, (int64_t)rb * (kCrtBM / 32),
-                (int64_t)(cb - sg.tile_begin) * (T::BN / 32));
+                args.Xd + pt0 * tile_stride + (int64_t)mi * kCrtSub, KB, plane_stride, kCrtModuli[mi], dst);
 }
 
 // A batch of problems in one launch.  Workgroups are dealt to the XCDs round-robin, so
@@ -357,7 +405,10 @@ __global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_batch_kernel(const Crt
     const int64_t t = args.chunk[x] + blockIdx.x / args.n_xcd;
     if (t >= args.chunk[x + 1]) return;
     const CrtItem it = args.items[t];
-    crt_tile<T>(lds, it.P, it.X, it.kblocks, (int64_t)args.D * kCrtSub, it.p, it.Y, it.nbc, it.brt, it.bct);
+    auto dst = [&](int bc) -> CrtBlockCol {
+        return {it.Y + ((int64_t)it.brt * it.nbc + it.bct + bc) * 1024, it.nbc * 1024};
+    };
+    crt_tile<T>(lds, it.P, it.X, it.kblocks, (int64_t)args.D * kCrtSub, it.p, dst);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -480,7 +531,7 @@ hipError_t launch_crt_split_cols(int D, const uint64_t *X, int64_t ldx, int64_t 
     return hipErrorInvalidValue;
 }
 
-int crt_tile_cols(int variant) { return variant == 0 ? CrtNarrow::BN : CrtWide::BN; }
+int crt_tile_cols(int variant) { return variant == 0 ? CrtNarrow::BN : variant == 1 ? CrtWide::BN : CrtWider::BN; }
 
 template <class T>
 static hipError_t launch_crt_t(int64_t grid, const CrtGemmArgs &a, hipStream_t s) {
@@ -492,7 +543,8 @@ hipError_t launch_crt_gemm(int variant, const CrtGemmArgs &a, hipStream_t s) {
     const int64_t grid = (int64_t)a.D * a.tiles_m * a.tiles_n;
     if (grid <= 0) return hipSuccess;
     if (grid > INT32_MAX) return hipErrorInvalidValue;
-    return variant == 0 ? launch_crt_t<CrtNarrow>(grid, a, s) : launch_crt_t<CrtWide>(grid, a, s);
+    if (variant == 0) return launch_crt_t<CrtNarrow>(grid, a, s);
+    return variant == 1 ? launch_crt_t<CrtWide>(grid, a, s) : launch_crt_t<CrtWider>(grid, a, s);
 }
 
 hipError_t launch_crt_combine(const CrtCombineArgs &a, hipStream_t s) {

@@ -58,18 +58,18 @@ __device__ __forceinline__ uint32_t crt_small_residue_word(int x) {
 
 // Product planes.  The GEMM of modulus i writes y_i = C_i mod p_i as one byte per entry (the
 // left operand's residues carry the factor (M / p_i)^{-1}, so y_i is already the CRT
-// coefficient).  A plane covers the output padded to whole GEMM tiles and is stored in the
-// accumulator order of v_mfma_i32_32x32x32_i8: 32 x 32 blocks, row-major over the padded grid,
-// each block as 64 lanes x 16 bytes, where lane l, byte r holds row 8 (r / 4) + 4 (l / 32) +
-// r % 4 and column l % 32 of the block.  Each lane thus stores its 16 results as one
-// contiguous 16-byte write.
+// coefficient).  A plane covers the output with its rows padded to whole 256-row GEMM tiles
+// and its columns to whole 128-column plane tiles, and is stored in the accumulator order of
+// v_mfma_i32_32x32x32_i8: 32 x 32 blocks, row-major over the padded grid, each block as 64
+// lanes x 16 bytes, where lane l, byte r holds row 8 (r / 4) + 4 (l / 32) + r % 4 and column
+// l % 32 of the block.  Each lane thus stores its 16 results as one contiguous 16-byte write.
 struct CrtSeg {
     uint8_t *Y;          // [D][plane] bytes of this output matrix
     int64_t n;           // valid columns
     int64_t nbc;         // 32-column blocks per padded row
     int64_t plane;       // bytes per modulus: padded rows x padded columns
-    int32_t tile_begin;  // first global GEMM column tile
-    int32_t pad;
+    int32_t tile_begin;  // first 128-column plane tile of this matrix among the launch's
+    int32_t tiles;       // and their count: the launch's matrices lie side by side
 };
 
 struct CrtGemmArgs {
@@ -78,7 +78,8 @@ struct CrtGemmArgs {
     int64_t m;
     int32_t kblocks, D;
     int32_t tiles_m;     // 256-row tiles
-    int32_t tiles_n;     // GEMM column tiles (128 or 256 wide) over all segments
+    int32_t tiles_n;     // GEMM column tiles (128, 256 or 384 wide) over all segments, which
+                         // may straddle two segments
     int32_t group_m, n_xcd, nseg, pad;
     CrtSeg seg[kMaxSegs];
 };

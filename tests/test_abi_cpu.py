@@ -142,8 +142,10 @@ def test_entry_points_reject_bad_arguments_before_device_work():
     assert bad.value == -1
     assert lib.hlb_set_option(999, 1) == 6
     assert lib.hlb_set_option(hlb.OPT_FORCE_KCHUNK, -5) == 1
-    for opt in (hlb.OPT_CRT_WIDE, hlb.OPT_F64_PLANES):
-        assert lib.hlb_set_option(opt, 0) == 0 and lib.hlb_set_option(opt, 1) == 0
+    assert lib.hlb_set_option(hlb.OPT_F64_PLANES, 0) == 0 and lib.hlb_set_option(hlb.OPT_F64_PLANES, 1) == 0
+    for v in (0, 1, 2):
+        assert lib.hlb_set_option(hlb.OPT_CRT_WIDE, v) == 0
+    assert lib.hlb_set_option(hlb.OPT_CRT_WIDE, 3) == 1 and lib.hlb_set_option(hlb.OPT_CRT_WIDE, -1) == 1
     assert lib.hlb_set_option(hlb.OPT_WS_CAP, -1) == 1
     assert lib.hlb_set_option(hlb.OPT_WS_CAP, 1 << 20) == 0 and lib.hlb_set_option(hlb.OPT_WS_CAP, 0) == 0
 

@@ -27,7 +27,7 @@ def _np(t):
     return t.cpu().numpy().view(np.uint64)
 
 
-@pytest.mark.parametrize("wide", [1, 0])
+@pytest.mark.parametrize("wide", [2, 1, 0])
 @pytest.mark.parametrize("dims", [(1, 1, 1, 1, 1), (33, 65, 17, 40, 1), (256, 128, 128, 128, 2),
                                   (200, 300, 130, 70, 3), (300, 64, 257, 1, 4), (64, 700, 64, 0, 2),
                                   (513, 129, 255, 129, 1), (100, 200, 600, 300, 1),
@@ -42,7 +42,7 @@ def test_cp_mm_crt_vs_oracle(dims, wide):
         PA, PB = hlb.cp_mm(_t(w.P), _t(A), _t(B), w.primes, p_absmax=w.p_absmax, form="int8_crt")
         got = (_np(PA), _np(PB))
     finally:
-        hlb.set_option(hlb.OPT_CRT_WIDE, 1)
+        hlb.set_option(hlb.OPT_CRT_WIDE, 2)
     wantA, wantB = oracle.cp_mm(w.P, A, B, w.primes)
     assert np.array_equal(got[0], wantA) and np.array_equal(got[1], wantB)
 
