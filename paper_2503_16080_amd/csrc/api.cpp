@@ -686,9 +686,9 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
             a.kblocks = (int)kblocks;
             a.kfold = kfold >= kblocks ? (int)kblocks + 1 : (int)kfold;  // >= kblocks: no fold
             a.tiles_m = (int)tiles_m;
-            // raster groups, measured at d = 8192: 16 row tiles for the digit GEMM (55.7 against
-            // 56.6 ms with 4; 8 and 32 are slower), 4 for the FP64 GEMMs
-            a.group_m = pl.form == HLB_FORM_INT8 ? 16 : 4;
+            // 4 row tiles per raster group.  For the digit GEMM, 16 was 1.5 % faster at d = 8192
+            // but read 1.3x the HBM bytes there and 1.4x at d = 16384, where it was slower.
+            a.group_m = 4;
             a.n_xcd = n_xcd;
             a.limb_bits = pl.limb_bits;
             int32_t tb = 0;
