@@ -253,6 +253,9 @@ hlb_status enqueue(const BatchLayout &lay, char *base, int grid, hipStream_t s) 
 
 
 // ------------------------------- multimodular batch -------------------------------------
+// Marks, before rebasing, a batch GEMM tile's plane tile that lies past its problem's outputs.
+constexpr uintptr_t kNoPlane = ~(uintptr_t)0;
+
 struct CrtBatchLayout {
     int D = 0;
     CrtScale scale;
@@ -329,6 +332,7 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
 
         const size_t p_off = (size_t)(uintptr_t)pj.out, x_off = plane_off;
         const size_t seg0 = lay.segs.size();
+        // the problem's output matrices lie side by side in 128-column plane tiles
         int64_t tb = 0;
         for (int l = 0; l < L; ++l) {
             for (int part = 0; part < 2; ++part) {
@@ -336,7 +340,7 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
                 if (n == 0) continue;
                 const uint64_t *X = (part == 0 ? p.A : p.B) + (int64_t)l * p.k * n;
                 uint64_t *C = (part == 0 ? p.PA : p.PB) + (int64_t)l * p.m * n;
-                const int64_t tg = (n + bn - 1) / bn;
+                const int64_t t128 = (n + 127) / 128;
                 CrtSplitJob xj;
                 std::memset(&xj, 0, sizeof(xj));
                 xj.wg_start = lay.split_wgs;
@@ -347,18 +351,18 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
                 xj.qc = primes[l];
                 xj.kblocks = (int32_t)kblocks;
                 xj.rows_side = 0;
-                xj.out = (int8_t *)(uintptr_t)(plane_off + (size_t)(tb * xsub * kblocks * sub));
+                xj.out = (int8_t *)(uintptr_t)(plane_off + (size_t)(tb * kblocks * sub));
                 lay.sjobs.push_back(xj);
-                lay.split_wgs += tg * xsub * kblocks;
+                lay.split_wgs += t128 * kblocks;
 
                 CrtSeg sg;
                 std::memset(&sg, 0, sizeof(sg));
                 sg.Y = (uint8_t *)(uintptr_t)y_off;
                 sg.n = n;
-                sg.nbc = tg * bn / 32;
-                sg.plane = (tiles_m * 256) * (tg * bn);
-                sg.tile_begin = (int32_t)(tb * xsub);
-                sg.tiles = (int32_t)(tg * xsub);
+                sg.nbc = t128 * 4;
+                sg.plane = (tiles_m * 256) * (t128 * 128);
+                sg.tile_begin = (int32_t)tb;
+                sg.tiles = (int32_t)t128;
                 lay.segs.push_back(sg);
 
                 CrtCombineJob cj;
@@ -383,35 +387,44 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
                 lay.cjobs.push_back(cj);
                 lay.combine_wgs += crt_combine_wgs(p.m, n);
                 y_off += (size_t)(D * sg.plane);
-                tb += tg;
+                tb += t128;
             }
         }
-        plane_off += (size_t)(tb * xsub * kblocks * sub);
-        const int64_t items = (int64_t)D * tiles_m * tb;
+        // GEMM tiles are xsub plane tiles wide; the last may reach xsub - 1 plane tiles past the
+        // problem's, so those are reserved too (never written, read only for discarded columns)
+        const int64_t tg = (tb + xsub - 1) / xsub;
+        plane_off += (size_t)((tb + xsub - 1) * kblocks * sub);
+        const int64_t items = (int64_t)D * tiles_m * tg;
         if (lay.total_items + items > INT32_MAX) return HLB_EINVAL;
-        // the problem's tiles: D moduli as D row bands of a (D tiles_m) x tb grid, walked
+        // the problem's tiles: D moduli as D row bands of a (D tiles_m) x tg grid, walked
         // group_m row tiles at a time, column by column (neighbours share operand panels);
-        // offsets are rebased once the workspace exists
+        // offsets are rebased once the workspace exists (kNoPlane marks a plane tile past the
+        // problem's outputs)
         const int64_t tile_stride = kblocks * sub, tm_all = (int64_t)D * tiles_m, group_m = 4;
-        size_t si = seg0;
         for (int64_t local = 0; local < items; ++local) {
-            const int64_t span = group_m * tb, gi = local / span, first = gi * group_m;
+            const int64_t span = group_m * tg, gi = local / span, first = gi * group_m;
             const int64_t gm = std::min(group_m, tm_all - first), in = local - gi * span;
             const int64_t rbv = first + in % gm, cb = in / gm;
             const int64_t mi = rbv / tiles_m, rb = rbv % tiles_m;
-            si = seg0;
-            while (si + 1 < lay.segs.size() && cb * xsub >= lay.segs[si + 1].tile_begin) ++si;
-            const CrtSeg &sg = lay.segs[si];
             CrtItem it;
             std::memset(&it, 0, sizeof(it));
             it.P = (const int8_t *)(uintptr_t)(p_off + (size_t)(2 * rb * tile_stride + mi * 128 * kBK8));
             it.X = (const int8_t *)(uintptr_t)(x_off + (size_t)(cb * xsub * tile_stride + mi * 128 * kBK8));
-            it.Y = (uint8_t *)(uintptr_t)((uintptr_t)sg.Y + (size_t)(mi * sg.plane));
-            it.nbc = sg.nbc;
+            for (int j = 0; j < kCrtItemCols; ++j) {
+                const int64_t pt = cb * xsub + j;
+                it.Y[j] = (uint8_t *)kNoPlane;
+                for (size_t si = seg0; si < lay.segs.size(); ++si) {
+                    const CrtSeg &sg = lay.segs[si];
+                    if (pt < sg.tile_begin || pt >= sg.tile_begin + sg.tiles) continue;
+                    it.Y[j] = (uint8_t *)(uintptr_t)((uintptr_t)sg.Y + (size_t)(mi * sg.plane));
+                    it.nbc[j] = sg.nbc;
+                    it.bct[j] = (int32_t)((pt - sg.tile_begin) * 4);
+                    break;
+                }
+            }
             it.kblocks = (int32_t)kblocks;
             it.p = kCrtModuli[mi];
             it.brt = (int32_t)(rb * 8);
-            it.bct = (int32_t)((cb * xsub - sg.tile_begin) * 4);
             lay.items.push_back(it);
         }
         lay.total_items += items;
@@ -455,7 +468,8 @@ void rebase_crt(CrtBatchLayout &lay, char *base) {
     for (CrtItem &it : lay.items) {
         it.P = (const int8_t *)(planes + (uintptr_t)it.P);
         it.X = (const int8_t *)(planes + (uintptr_t)it.X);
-        it.Y = (uint8_t *)(ybytes + (uintptr_t)it.Y);
+        for (int j = 0; j < kCrtItemCols; ++j)
+            it.Y[j] = (uintptr_t)it.Y[j] == kNoPlane ? nullptr : (uint8_t *)(ybytes + (uintptr_t)it.Y[j]);
     }
     for (CrtCombineJob &j : lay.cjobs) j.a.Y = (const uint8_t *)(ybytes + (uintptr_t)j.a.Y);
 }

@@ -404,9 +404,12 @@ __global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_batch_kernel(const Crt
     const int x = (int)(blockIdx.x % args.n_xcd);
     const int64_t t = args.chunk[x] + blockIdx.x / args.n_xcd;
     if (t >= args.chunk[x + 1]) return;
-    const CrtItem it = args.items[t];
+    const CrtItem &it = args.items[t];  // read in place: the epilogue indexes its arrays by wave
+    static_assert(T::XSUB == kCrtItemCols, "one destination per plane tile of the batch tile");
     auto dst = [&](int bc) -> CrtBlockCol {
-        return {it.Y + ((int64_t)it.brt * it.nbc + it.bct + bc) * 1024, it.nbc * 1024};
+        const int j = bc / 4;
+        if (!it.Y[j]) return {nullptr, 0};
+        return {it.Y[j] + ((int64_t)it.brt * it.nbc[j] + it.bct[j] + bc % 4) * 1024, it.nbc[j] * 1024};
     };
     crt_tile<T>(lds, it.P, it.X, it.kblocks, (int64_t)args.D * kCrtSub, it.p, dst);
 }
@@ -577,11 +580,11 @@ hipError_t launch_crt_gemm_batch(const CrtBatchArgs &a, hipStream_t s) {
     for (int x = 0; x < a.n_xcd; ++x) longest = std::max<int64_t>(longest, a.chunk[x + 1] - a.chunk[x]);
     const int64_t grid = longest * a.n_xcd;
     if (grid > INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(crt_gemm_batch_kernel<CrtWide>, dim3((unsigned)grid), dim3(CrtWide::THREADS), 0, s, a);
+    hipLaunchKernelGGL(crt_gemm_batch_kernel<CrtWider>, dim3((unsigned)grid), dim3(CrtWider::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
-int crt_batch_tile_cols() { return CrtWide::BN; }
+int crt_batch_tile_cols() { return CrtWider::BN; }
 
 hipError_t launch_crt_combine_batch(const CrtCombineJob *jobs, int njobs, int64_t total_wgs, hipStream_t s) {
     if (total_wgs <= 0 || njobs <= 0) return hipSuccess;
