@@ -318,31 +318,31 @@ __device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const in
             }
         }
     } else {
-    Frags f0, f1;
-    read_frags(f0, 0, 0);
+        Frags f0, f1;
+        read_frags(f0, 0, 0);
 #pragma unroll 1
-    for (int kb = 0; kb < KB; kb += G) {
+        for (int kb = 0; kb < KB; kb += G) {
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int st = kb + g;
-            if (st >= KB) break;
-            const int cur = st % kCrtNbuf;
-            read_frags(f1, cur, 1);
-            mfmas(f0);
-            interleave_reads_with_mfmas<MB + NB>();
-            if (g == G - 1 || st + 1 == KB) {
-                wait_lds_after_mfmas();
-                // stages issued so far: up to kb + NBUF - 1; the next group must have landed
-                wait_vmcnt(outstanding(kb + 2 * G - 1, kb + kCrtNbuf - 1));
-                stage_barrier();
+            for (int g = 0; g < G; ++g) {
+                const int st = kb + g;
+                if (st >= KB) break;
+                const int cur = st % kCrtNbuf;
+                read_frags(f1, cur, 1);
+                mfmas(f0);
+                interleave_reads_with_mfmas<MB + NB>();
+                if (g == G - 1 || st + 1 == KB) {
+                    wait_lds_after_mfmas();
+                    // stages issued so far: up to kb + NBUF - 1; the next group must have landed
+                    wait_vmcnt(outstanding(kb + 2 * G - 1, kb + kCrtNbuf - 1));
+                    stage_barrier();
 #pragma unroll
-                for (int h = 0; h < G; ++h)
-                    if (kb + h + kCrtNbuf < KB) gload(kb + h + kCrtNbuf, (kb + h) % kCrtNbuf);
+                    for (int h = 0; h < G; ++h)
+                        if (kb + h + kCrtNbuf < KB) gload(kb + h + kCrtNbuf, (kb + h) % kCrtNbuf);
+                }
+                if (st + 1 < KB) read_frags(f0, (st + 1) % kCrtNbuf, 0);
+                mfmas(f1);
             }
-            if (st + 1 < KB) read_frags(f0, (st + 1) % kCrtNbuf, 0);
-            mfmas(f1);
         }
-    }
     }
 
     // epilogue: one 16-byte store per 32 x 32 block and lane
