@@ -66,12 +66,13 @@ struct DevInfo {
     int checked = 0;
     bool ok = false;
     int n_xcd = 8;
+    int cus = 256;
     bool pool_set = false;
 };
 static std::mutex g_dev_mu;
 static DevInfo g_dev[64];
 
-hlb_status device_ready(int *n_xcd) {
+hlb_status device_ready(int *n_xcd, int *cus) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return HLB_EDEVICE;
     std::lock_guard<std::mutex> g(g_dev_mu);
@@ -83,6 +84,7 @@ hlb_status device_ready(int *n_xcd) {
         d.ok = std::strncmp(p.gcnArchName, "gfx950", 6) == 0;
         // gfx950 has 32 CUs per XCD; a partitioned device exposes fewer XCDs
         d.n_xcd = std::max(1, p.multiProcessorCount / 32);
+        d.cus = std::max(1, p.multiProcessorCount);
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
             uint64_t thr = UINT64_MAX;  // keep freed workspace cached in the pool
@@ -91,6 +93,7 @@ hlb_status device_ready(int *n_xcd) {
     }
     if (!d.ok) return HLB_EUNSUP;
     if (n_xcd) *n_xcd = d.n_xcd;
+    if (cus) *cus = d.cus;
     return HLB_OK;
 }
 

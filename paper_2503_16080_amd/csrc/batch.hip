@@ -640,11 +640,8 @@ hlb_status run_crt_batch(const hlb_cpmm_problem *probs, int count, const uint64_
 }
 
 int persistent_grid(const BatchLayout &lay) {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t p;
-        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
-    }
+    int n_xcd = 8, cus = 256;
+    (void)device_ready(&n_xcd, &cus);  // cached per device
     return (int)std::min<int64_t>(cus, lay.total_items);
 }
 

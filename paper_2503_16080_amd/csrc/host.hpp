@@ -57,7 +57,7 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
 void choose_class(Plan *pl, int64_t m, int64_t n, int64_t k);
 int i8_digits_for(uint64_t vmax);
 hlb_status check_modulus(uint64_t q);
-hlb_status device_ready(int *n_xcd);
+hlb_status device_ready(int *n_xcd, int *cus = nullptr);
 void fill_seg(Seg &s, uint64_t q, int limb_bits);
 hlb_status ws_alloc(void **p, size_t bytes, hipStream_t s);
 void ws_free(void *p, hipStream_t s);
