@@ -28,9 +28,14 @@
  *    Argument and planning errors are reported synchronously, before anything is enqueued.
  *    Entry points documented as "synchronous" synchronise `stream` before returning.
  *  - Moduli: 2 <= q < 2^52.
- *  - Workspace (digit or residue planes, the multimodular bytes, FP64 double planes) is
- *    allocated by the library from a stream-ordered pool and freed in stream order;
- *    hlb_release() returns pooled memory.
+ *  - Workspace (digit or residue planes, the multimodular bytes, FP64 double planes) comes
+ *    from one device block the library keeps per (device, stream): each call carves its
+ *    buffers from its stream's block, which grows to the largest workspace a call on that
+ *    stream has needed and is reused by the next call in stream order.  Concurrent calls on
+ *    one stream from several host threads take turns on the block.  Under graph capture the
+ *    workspace is a stream-ordered pool allocation owned by the graph.  hlb_release()
+ *    returns every block; a destroyed stream's block is kept until then, so a stream must
+ *    have finished its library work before it is destroyed.
  *  - Calls on different streams may run concurrently.
  *  - The functions are not re-entrant during hlb_release().
  */
@@ -283,7 +288,8 @@ int hlb_tune_class(int x_digits, int64_t m, int64_t n, int64_t k);
 hlb_status hlb_profile_read(const char *name, int64_t *launches, double *total_ms);
 hlb_status hlb_profile_reset(void);
 
-/* Frees pooled workspace and cached batch graphs (synchronises the device). */
+/* Frees the per-stream workspace blocks, pooled memory and cached batch graphs
+ * (synchronises the device). */
 hlb_status hlb_release(void);
 
 /* ------------------------------------------------------------------------------------ */

@@ -418,6 +418,88 @@ void ws_free(void *p, hipStream_t s) {
     if (p) (void)hipFreeAsync(p, s);
 }
 
+// Per-stream blocks.  A pool allocation per call was measured to degrade: after a few hundred
+// calls alternating shapes and forms, hipMallocAsync averaged 1.3 ms and reached seconds.
+struct WsSlot {
+    std::mutex mu;  // held by the lease of the call using the block
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+static std::mutex g_slots_mu;
+static std::map<std::pair<int, hipStream_t>, WsSlot *> g_slots;
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+hlb_status WsLease::take(hipStream_t s, const size_t *bytes, void **ptrs, int n) {
+    const int64_t cap = g_ws_cap.load();
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        ptrs[i] = nullptr;
+        if (bytes[i] == 0) continue;
+        if (cap > 0 && ws_bucket(bytes[i]) > (size_t)cap) return HLB_ENOMEM;
+        total += align256(bytes[i]);
+    }
+    if (total == 0) return HLB_OK;
+    s_ = s;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    char *base = nullptr;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+        if (hipMallocAsync(&own_, total, s) != hipSuccess) {
+            (void)hipGetLastError();
+            own_ = nullptr;
+            return HLB_ENOMEM;
+        }
+        base = (char *)own_;
+    } else {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return HLB_EDEVICE;
+        {
+            std::lock_guard<std::mutex> g(g_slots_mu);
+            WsSlot *&sl = g_slots[{dev, s}];
+            if (!sl) sl = new WsSlot;
+            slot_ = sl;
+        }
+        slot_->mu.lock();
+        if (slot_->bytes < total) {
+            // the old block's last users precede this call in stream order
+            if (slot_->p) (void)hipFreeAsync(slot_->p, s);
+            slot_->p = nullptr;
+            slot_->bytes = 0;
+            const size_t want = ws_bucket(total);
+            if (hipMallocAsync(&slot_->p, want, s) != hipSuccess) {
+                (void)hipGetLastError();
+                slot_->p = nullptr;
+                return HLB_ENOMEM;  // the destructor unlocks
+            }
+            slot_->bytes = want;
+        }
+        base = (char *)slot_->p;
+    }
+    for (int i = 0; i < n; ++i) {
+        if (bytes[i] == 0) continue;
+        ptrs[i] = base;
+        base += align256(bytes[i]);
+    }
+    return HLB_OK;
+}
+
+WsLease::~WsLease() {
+    if (own_) (void)hipFreeAsync(own_, s_);
+    if (slot_) slot_->mu.unlock();
+}
+
+// Frees every stream's block (the device work that used them must have completed).
+void ws_release_all() {
+    std::lock_guard<std::mutex> g(g_slots_mu);
+    for (auto &kv : g_slots) {
+        std::lock_guard<std::mutex> h(kv.second->mu);
+        if (kv.second->p) (void)hipFreeAsync(kv.second->p, nullptr);
+        kv.second->p = nullptr;
+        kv.second->bytes = 0;
+    }
+    (void)hipDeviceSynchronize();
+}
+
 // ---------------------------------------------------------------------------------------
 // One GEMM launch over up to kMaxSegs output segments sharing the left operand.
 // ---------------------------------------------------------------------------------------
@@ -465,17 +547,16 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
     }
 
     void *wsP = nullptr, *wsX = nullptr, *wsY = nullptr;
-    auto release = [&]() {
-        ws_free(wsP, s);
-        ws_free(wsX, s);
-        ws_free(wsY, s);
-    };
-    hlb_status st = ws_alloc(&wsP, (size_t)(t128_m * kblocks * sub), s);
-    if (st == HLB_OK) st = ws_alloc(&wsX, (size_t)((tn_total + xsub - 1) * kblocks * sub), s);
-    if (st == HLB_OK) st = ws_alloc(&wsY, (size_t)ybytes, s);
-    if (st != HLB_OK) {
-        release();
-        return st;
+    WsLease lease;
+    {
+        const size_t sizes[3] = {(size_t)(t128_m * kblocks * sub), (size_t)((tn_total + xsub - 1) * kblocks * sub),
+                                 (size_t)ybytes};
+        void *ptrs[3];
+        const hlb_status st = lease.take(s, sizes, ptrs, 3);
+        if (st != HLB_OK) return st;
+        wsP = ptrs[0];
+        wsX = ptrs[1];
+        wsY = ptrs[2];
     }
     // offsets of each right operand's split tiles (128 wide) and product planes
     std::vector<int64_t> x_tile0(rights.size()), y_off(rights.size());
@@ -565,29 +646,24 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
 
     for (size_t i = 0; i < rights.size(); ++i)
         if (!split_x(i, s)) {
-            release();
             return HLB_EDEVICE;
         }
     for (const LeftSpec &L : lefts) {
         if (L.m == 0) continue;
         if (!split_p(L, s)) {
-            release();
             return HLB_EDEVICE;
         }
         for (size_t first = 0; first < rights.size(); first += kMaxSegs) {
             const size_t last = std::min(rights.size(), first + kMaxSegs);
             if (!gemm(L, first, last, s)) {
-                release();
                 return HLB_EDEVICE;
             }
             for (size_t i = first; i < last; ++i)
                 if (!combine(L, i, s)) {
-                    release();
                     return HLB_EDEVICE;
                 }
         }
     }
-    release();
     return HLB_OK;
 }
 
@@ -630,18 +706,14 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
         p_tile = f64_plane_bytes_p(1, 1);
         x_tile = f64_plane_bytes_x(pl.nx, 1, 1);
     }
-    auto release = [&]() {
-        ws_free(wsP, s);
-        ws_free(wsX, s);
-    };
+    WsLease lease;
     if (pl.form == HLB_FORM_INT8 || planes) {
-        hlb_status st = ws_alloc(&wsP, (size_t)(tiles_mmax * kblocks * p_tile), s);
+        const size_t sizes[2] = {(size_t)(tiles_mmax * kblocks * p_tile), (size_t)(tiles_total * kblocks * x_tile)};
+        void *ptrs[2];
+        const hlb_status st = lease.take(s, sizes, ptrs, 2);
         if (st != HLB_OK) return st;
-        st = ws_alloc(&wsX, (size_t)(tiles_total * kblocks * x_tile), s);
-        if (st != HLB_OK) {
-            release();
-            return st;
-        }
+        wsP = ptrs[0];
+        wsX = ptrs[1];
         int64_t t0 = 0;
         for (size_t i = 0; i < rights.size(); ++i) {
             ProfScope ps(planes ? "prep_x" : "split_x", s);
@@ -653,7 +725,6 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
                        : launch_split_cols_i8(pl.nx, pl.bn, rights[i].X, rights[i].ldx, k, rights[i].n,
                                               (int)seg_tiles[i], (int)kblocks, dst, s);
             if (e != hipSuccess) {
-                release();
                 return HLB_EDEVICE;
             }
             t0 += seg_tiles[i];
@@ -671,7 +742,6 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
                        : launch_split_rows_i8(pl.np, pl.bm, L.P, L.ldp, L.m, k, (int)tiles_m, (int)kblocks,
                                               (int8_t *)wsP, s);
             if (e != hipSuccess) {
-                release();
                 return HLB_EDEVICE;
             }
         }
@@ -728,12 +798,10 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
                 e = launch_gemm_f64(pl.np, pl.nx, a, s);
             }
             if (e != hipSuccess) {
-                release();
                 return HLB_EDEVICE;
             }
         }
     }
-    release();
     return HLB_OK;
 }
 
@@ -1129,6 +1197,7 @@ int hlb_tune_class(int x_digits, int64_t m, int64_t n, int64_t k) {
 hlb_status hlb_release(void) {
     if (hipDeviceSynchronize() != hipSuccess) return HLB_EDEVICE;
     batch_release();
+    ws_release_all();
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return HLB_EDEVICE;
     hipMemPool_t pool;

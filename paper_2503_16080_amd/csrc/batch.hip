@@ -583,14 +583,16 @@ hlb_status run_crt_batch(const hlb_cpmm_problem *probs, int count, const uint64_
     if (lay.total_items == 0) return HLB_OK;
     if (!opt_batch_graph()) {
         void *ws = nullptr;
-        if ((st = ws_alloc(&ws, lay.bytes, s)) != HLB_OK) return st;
+        WsLease lease;
+        const size_t bytes = lay.bytes;
+        if ((st = lease.take(s, &bytes, &ws, 1)) != HLB_OK) return st;
         rebase_crt(lay, (char *)ws);
         std::vector<char> img = crt_descriptor_image(lay);
         if (hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, s) != hipSuccess) st = HLB_EDEVICE;
         if (st == HLB_OK) st = enqueue_crt(lay, (char *)ws, s);
         // the host image must outlive the copy
         if (hipStreamSynchronize(s) != hipSuccess && st == HLB_OK) st = HLB_EDEVICE;
-        ws_free(ws, s);
+        // the lease returns the workspace block to the stream
         return st;
     }
     int dev = 0;
@@ -720,14 +722,16 @@ extern "C" hlb_status hlb_cp_mm_batch(const hlb_cpmm_problem *probs, int count, 
     if (!opt_batch_graph()) {
         // eager: stream-ordered workspace, descriptors uploaded, four launches
         void *ws = nullptr;
-        if ((st = ws_alloc(&ws, lay.bytes, s)) != HLB_OK) return st;
+        WsLease lease;
+        const size_t bytes = lay.bytes;
+        if ((st = lease.take(s, &bytes, &ws, 1)) != HLB_OK) return st;
         rebase(lay, (char *)ws);
         std::vector<char> img = descriptor_image(lay);
         if (hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, s) != hipSuccess) st = HLB_EDEVICE;
         if (st == HLB_OK) st = enqueue(lay, (char *)ws, grid, s);
         // the host image must outlive the copy
         if (hipStreamSynchronize(s) != hipSuccess && st == HLB_OK) st = HLB_EDEVICE;
-        ws_free(ws, s);
+        // the lease returns the workspace block to the stream
         return st;
     }
 

@@ -61,6 +61,29 @@ hlb_status device_ready(int *n_xcd, int *cus = nullptr);
 void fill_seg(Seg &s, uint64_t q, int limb_bits);
 hlb_status ws_alloc(void **p, size_t bytes, hipStream_t s);
 void ws_free(void *p, hipStream_t s);
+void ws_release_all();
+
+// The workspace of one call: n buffers carved, 256-byte aligned, from one block kept with the
+// call's stream (device, stream) and reused by the next call on it.  Calls on one stream run in
+// stream order, so the block is free again once a call is enqueued; the lease also holds the
+// stream's block against concurrent calls from other host threads until it is destroyed.  The
+// block grows to the largest workspace a call on the stream has needed (ws_release_all returns
+// it).  Under graph capture the buffers come from the pool instead, owned by the graph.
+struct WsSlot;
+class WsLease {
+  public:
+    WsLease() = default;
+    WsLease(const WsLease &) = delete;
+    WsLease &operator=(const WsLease &) = delete;
+    ~WsLease();
+    // HLB_ENOMEM when a buffer is above the workspace cap or the block cannot grow.
+    hlb_status take(hipStream_t s, const size_t *bytes, void **ptrs, int n);
+
+  private:
+    WsSlot *slot_ = nullptr;
+    void *own_ = nullptr;
+    hipStream_t s_ = nullptr;
+};
 int64_t opt_force_kchunk();
 bool opt_batch_graph();
 void batch_release();

@@ -1,0 +1,69 @@
+"""The library's per-stream workspace block: calls of alternating shapes and forms reuse and
+grow one block per stream, two streams keep separate blocks, and hlb_release returns them.
+Every result is checked bit for bit against the oracle (the plain definition of CP-MM)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2503_16080_amd as hlb
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _t(a):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    return torch.from_numpy(a).to(DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+# (m, k, n, L): small, large, small again, so the block grows and is then reused
+SHAPES = [(40, 70, 33, 2), (300, 1100, 520, 3), (64, 200, 64, 1), (513, 260, 300, 2), (33, 65, 17, 1)]
+FORMS = ["int8_crt", "int8", "fp64"]
+
+
+def _case(i, shape):
+    m, k, n, L = shape
+    w = wl.cpmm_uniform(7100 + i, m, k, n, 50, L)
+    want = oracle.cp_mm(w.P, w.A, w.B, w.primes)
+    return w, want
+
+
+def test_alternating_shapes_and_forms_on_one_stream():
+    cases = [_case(i, s) for i, s in enumerate(SHAPES)]
+    for rep in range(2):
+        for i, (w, want) in enumerate(cases):
+            form = FORMS[(i + rep) % len(FORMS)]
+            PA, PB = hlb.cp_mm(_t(w.P), _t(w.A), _t(w.B), w.primes, p_absmax=w.p_absmax, form=form)
+            assert np.array_equal(_np(PA), want[0]) and np.array_equal(_np(PB), want[1]), (rep, i, form)
+
+
+def test_two_streams_without_host_sync_between_calls():
+    cases = [_case(20 + i, s) for i, s in enumerate(SHAPES[:4])]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    inputs = [(_t(w.P), _t(w.A), _t(w.B)) for w, _ in cases]
+    torch.cuda.synchronize()
+    outs = []
+    for i, ((w, _), (P, A, B)) in enumerate(zip(cases, inputs)):
+        st = streams[i % 2]
+        with torch.cuda.stream(st):
+            outs.append(hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form=FORMS[i % 2], stream=st))
+    torch.cuda.synchronize()
+    for (w, want), (PA, PB) in zip(cases, outs):
+        assert np.array_equal(_np(PA), want[0]) and np.array_equal(_np(PB), want[1])
+
+
+def test_release_between_calls():
+    w, want = _case(40, SHAPES[1])
+    for _ in range(2):
+        PA, PB = hlb.cp_mm(_t(w.P), _t(w.A), _t(w.B), w.primes, p_absmax=w.p_absmax, form="int8_crt")
+        assert np.array_equal(_np(PA), want[0]) and np.array_equal(_np(PB), want[1])
+        hlb.release()
