@@ -1,6 +1,7 @@
 """The library's per-stream workspace block: calls of alternating shapes and forms reuse and
-grow one block per stream, two streams keep separate blocks, and hlb_release returns them.
-Every result is checked bit for bit against the oracle (the plain definition of CP-MM)."""
+grow one block per stream, two streams keep separate blocks, hlb_release returns them, and a
+caller can capture a call in a graph (its workspace then belongs to the graph).  Every result
+is checked bit for bit against the oracle (the plain definition of CP-MM)."""
 import numpy as np
 import pytest
 import torch
@@ -67,3 +68,29 @@ def test_release_between_calls():
         PA, PB = hlb.cp_mm(_t(w.P), _t(w.A), _t(w.B), w.primes, p_absmax=w.p_absmax, form="int8_crt")
         assert np.array_equal(_np(PA), want[0]) and np.array_equal(_np(PB), want[1])
         hlb.release()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_caller_captures_cp_mm_in_a_graph(form):
+    # under capture the workspace is a graph-owned allocation; every replay, with eager work
+    # and synchronisations between replays, matches the oracle
+    w, want = _case(60, (300, 700, 260, 2))
+    P, A, B = _t(w.P), _t(w.A), _t(w.B)
+    PA = torch.empty((2, 300, 260), dtype=torch.int64, device=DEV)
+    PB = torch.empty_like(PA)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form=form, out=(PA, PB), stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form=form, out=(PA, PB), stream=s)
+    for _ in range(3):
+        PA.fill_(7)
+        PB.fill_(7)
+        torch.cuda.synchronize()
+        g.replay()
+        assert np.array_equal(_np(PA), want[0]) and np.array_equal(_np(PB), want[1])
+        torch.randn(1000, device=DEV).sum().item()
