@@ -25,7 +25,7 @@ def _np(t):
     return t.cpu().numpy().view(np.uint64)
 
 
-@pytest.mark.parametrize("form", ["int8", "fp64"])
+@pytest.mark.parametrize("form", ["int8_crt", "int8", "fp64"])
 def test_encrypted_product_decrypts_to_plaintext_product(form):
     # ct = (A, B) with A S + B = encode(M) + E (mod q_i); after CP-MM,
     # (P A) S + P B = P (encode(M) + E) (mod q_i) exactly, and decoding gives P M within the

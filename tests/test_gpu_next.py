@@ -50,7 +50,8 @@ def test_rescale_vs_oracle_and_edges():
     assert np.array_equal(got, oracle.rescale(X, primes))
 
 
-def test_cp_mm_then_rescale_decrypts_to_scaled_product():
+@pytest.mark.parametrize("form", ["int8_crt", "int8"])
+def test_cp_mm_then_rescale_decrypts_to_scaled_product(form):
     # Algorithm alg:pcmm end to end: ct over L primes -> (P A, P B) -> Rescale by the last
     # prime q_L -> decryption under the same secret with the first L-1 primes gives
     # P (encode(M) + E) / q_L up to the rescaling error, i.e. k |S| / 2 + 1/2 per entry.
@@ -59,7 +60,7 @@ def test_cp_mm_then_rescale_decrypts_to_scaled_product():
     Menc = oracle.encode(d.M, delta)
     B = oracle.encrypt(d.A, d.S, Menc, d.E, d.primes)
     P = oracle.round_half_up(d.U * 2.0 ** d.p_scale_bits)
-    PA, PB = hlb.cp_mm(_t(P), _t(d.A), _t(B), d.primes, p_absmax=1 << d.p_scale_bits, form="int8")
+    PA, PB = hlb.cp_mm(_t(P), _t(d.A), _t(B), d.primes, p_absmax=1 << d.p_scale_bits, form=form)
     rA, rB = hlb.rescale(PA, d.primes), hlb.rescale(PB, d.primes)
     # the rescaled parts equal the oracle's rescale of the oracle's product, bit for bit
     oA, oB = oracle.cp_mm(P, d.A, B, d.primes)
@@ -75,7 +76,7 @@ def test_cp_mm_then_rescale_decrypts_to_scaled_product():
     assert err <= n * 1 * 0.5 + 0.5 + 1e-9   # rounding of A' and B' by at most 1/2 each
 
 
-@pytest.mark.parametrize("form", ["int8", "fp64"])
+@pytest.mark.parametrize("form", ["int8_crt", "int8", "fp64"])
 def test_precomputation_online_step_is_b_part_only(form):
     # CP-MM with precomputation: the online work is the single product B' = P B per prime
     # (nA = 0), bit-identical to the b-part of the full CP-MM.

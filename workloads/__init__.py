@@ -176,3 +176,60 @@ CONFIGS = {
     4: dict(kind="cp_mm_batch", count=64, bits=45, L=4, form="int8", seed=1004),
     5: dict(kind="cp_mm", d=16384, bits=50, L=2, form="int8", seed=1005),
 }
+
+
+# ---------------------------------------------------------------------------------------
+# Device-side generators for the large configurations: the same distributions, drawn with a
+# seeded torch generator on the GPU (a d = 16384 ciphertext is 10 GiB of residues, too slow to
+# draw on the host).  Both the library and the oracle see these exact tensors: the checks copy
+# them to the host.
+# ---------------------------------------------------------------------------------------
+
+def device_generator(seed: int, device="cuda"):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return g
+
+
+def plaintext_matrix_device(g, m: int, k: int, scale_bits: int = 20, device="cuda"):
+    """P = floor(2^scale_bits * U + 1/2) with U uniform in [-1, 1], int64 on the device."""
+    import torch
+    U = torch.rand((m, k), dtype=torch.float64, device=device, generator=g) * 2.0 - 1.0
+    return torch.floor(U * float(1 << scale_bits) + 0.5).to(torch.int64)
+
+
+def uniform_residues_device(g, shape, q: int, device="cuda"):
+    """Entries uniform in [0, q), int64 on the device (bit-identical to uint64 residues)."""
+    import torch
+    return torch.randint(0, int(q), tuple(shape), dtype=torch.int64, device=device, generator=g)
+
+
+def cpmm_uniform_device(seed: int, m: int, k: int, n: int, bits: int, L: int, scale_bits: int = 20,
+                        device="cuda"):
+    """(primes, P, A, B) of a CP-MM drawn on the device: the distributions of cpmm_uniform."""
+    import torch
+    g = device_generator(seed, device)
+    primes = ntt_primes(bits, L, skip=seed % 8)
+    P = plaintext_matrix_device(g, m, k, scale_bits, device)
+    A = torch.stack([uniform_residues_device(g, (k, n), q, device) for q in primes])
+    B = torch.stack([uniform_residues_device(g, (k, n), q, device) for q in primes])
+    return primes, P, A, B
+
+
+def batch_problems_device(seed: int = 1004, count: int = 64, bits: int = 45, L: int = 4,
+                          scale_bits: int = 20, device="cuda"):
+    """The batch workload: `count` CP-MMs with (m, d) from batch_shapes(seed), n = d, over the
+    L primes of `bits` bits; returns (primes, shapes, problems) with problems as dicts of
+    device tensors P (m x d), A and B ([L][d][d])."""
+    g = device_generator(seed, device)
+    primes = ntt_primes(bits, L, skip=seed % 8)
+    shapes = batch_shapes(seed, count)
+    probs = []
+    import torch
+    for (m, d) in shapes:
+        P = plaintext_matrix_device(g, m, d, scale_bits, device)
+        A = torch.stack([uniform_residues_device(g, (d, d), q, device) for q in primes])
+        B = torch.stack([uniform_residues_device(g, (d, d), q, device) for q in primes])
+        probs.append(dict(P=P, A=A, B=B, p_absmax=1 << scale_bits))
+    return primes, shapes, probs
