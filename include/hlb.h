@@ -90,7 +90,8 @@ hlb_status hlb_mod_pp_mm(uint64_t q, int64_t m, int64_t k, int64_t n,
  *   P:  m x k signed plaintext (ldp >= k) with every |P[i][j]| <= p_absmax.
  *       The same P serves all primes and both parts: it is split into digits once.
  *   p_absmax: a bound on |P| (1 <= p_absmax < 2^52).  Pass 0 to have the library measure
- *       it on the device (that makes the call synchronous).
+ *       it on the device (that makes the call synchronous, and on a stream under graph
+ *       capture it is refused with HLB_EINVAL before anything is enqueued).
  *   A:  [L][k][nA] residues, dense (prime l's matrix at A + l*k*nA); B: [L][k][nB].
  *   PA: [L][m][nA] output, dense; PB: [L][m][nB] output, dense.
  *   primes: host array of L moduli, each 2 <= q < 2^52.
@@ -201,14 +202,14 @@ hlb_status hlb_cp_mm_batch(const hlb_cpmm_problem *probs, int count, const uint6
 
 /*
  * Synchronous check that every entry of a rows x cols residue matrix (row stride ld) is
- * < q.  *first_bad (host) receives the row-major linear index (row*cols + col) of the first
+ * < q (HLB_EINVAL on a stream under graph capture).  *first_bad (host) receives the row-major linear index (row*cols + col) of the first
  * offending entry, or -1.  Returns HLB_ERANGE if one exists, HLB_OK otherwise.
  */
 hlb_status hlb_validate_residues(const uint64_t *X, int64_t rows, int64_t cols, int64_t ld,
                                  uint64_t q, int64_t *first_bad, void *stream);
 
 /* Synchronous: *absmax (host) = max |P[i][j]| over an m x k signed matrix (row stride ld);
- * values equal to INT64_MIN report INT64_MAX. */
+ * values equal to INT64_MIN report INT64_MAX.  HLB_EINVAL on a stream under graph capture. */
 hlb_status hlb_plaintext_absmax(const int64_t *P, int64_t m, int64_t k, int64_t ld,
                                 int64_t *absmax, void *stream);
 

@@ -805,11 +805,23 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
     return HLB_OK;
 }
 
+// True when `s` is being captured into a graph (or its capture state cannot be read).
+bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+// Synchronous reduction with a host result: refused (before anything is enqueued) on a stream
+// under capture, where neither the copy to the host nor the synchronization may happen.
 hlb_status measure_absmax(const int64_t *P, int64_t m, int64_t k, int64_t ld, int64_t *out, hipStream_t s) {
+    if (stream_capturing(s)) return HLB_EINVAL;
     unsigned long long *d = nullptr;
-    if (hipMallocAsync((void **)&d, sizeof(*d), s) != hipSuccess) return HLB_ENOMEM;
+    if (hipMallocAsync((void **)&d, sizeof(*d), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return HLB_ENOMEM;
+    }
     hlb_status st = HLB_OK;
-    if (hipMemsetAsync(d, 0, sizeof(*d), s) != hipSuccess) st = HLB_EDEVICE;
+    if (launch_zero((uint64_t *)d, 1, 1, 1, s) != hipSuccess) st = HLB_EDEVICE;
     if (st == HLB_OK && m > 0 && k > 0 && launch_absmax(P, m, k, ld, d, s) != hipSuccess) st = HLB_EDEVICE;
     unsigned long long h = 0;
     if (st == HLB_OK && hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) st = HLB_EDEVICE;
@@ -849,6 +861,36 @@ static hlb_status cp_mm_prepare(int64_t m, int64_t k, int64_t nA, int64_t nB, co
         if ((uint64_t)*p_absmax >= kMaxModulus) return HLB_ERANGE;
     }
     return HLB_OK;
+}
+
+hlb_status cp_mm_entry(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp, int64_t p_absmax,
+                       const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L, uint64_t *PA, uint64_t *PB,
+                       int form, hipStream_t s) {
+    uint64_t qmin = 0, qmax = 0;
+    int n_xcd = 8;
+    bool nothing = false;
+    hlb_status st = cp_mm_prepare(m, k, nA, nB, P, ldp, &p_absmax, A, B, primes, L, PA, PB, s, &qmin, &qmax,
+                                  &n_xcd, &nothing);
+    if (st != HLB_OK || nothing) return st;
+    Plan pl;
+    if ((st = plan(1, k, qmax, std::max<int64_t>(p_absmax, 1), form, &pl)) != HLB_OK) return st;
+    auto_for_shape(&pl, form, m, std::max(nA, nB), k, qmax, std::max<int64_t>(p_absmax, 1));
+    choose_class(&pl, m, std::max(nA, nB), k);
+    std::vector<RightSpec> rights;
+    LeftSpec left{P, ldp, m, {}, {}};
+    for (int l = 0; l < L; ++l) {
+        if (nA > 0) {
+            rights.push_back({A + (int64_t)l * k * nA, nA, nA, primes[l]});
+            left.C.push_back(PA + (int64_t)l * m * nA);
+            left.ldc.push_back(nA);
+        }
+        if (nB > 0) {
+            rights.push_back({B + (int64_t)l * k * nB, nB, nB, primes[l]});
+            left.C.push_back(PB + (int64_t)l * m * nB);
+            left.ldc.push_back(nB);
+        }
+    }
+    return run_products(pl, {left}, rights, k, n_xcd, s);
 }
 
 }  // namespace hlb
@@ -910,32 +952,7 @@ hlb_status hlb_mod_pp_mm(uint64_t q, int64_t m, int64_t k, int64_t n, const uint
 hlb_status hlb_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp,
                      int64_t p_absmax, const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L,
                      uint64_t *PA, uint64_t *PB, int form, void *stream) {
-    const hipStream_t s = (hipStream_t)stream;
-    uint64_t qmin = 0, qmax = 0;
-    int n_xcd = 8;
-    bool nothing = false;
-    hlb_status st = cp_mm_prepare(m, k, nA, nB, P, ldp, &p_absmax, A, B, primes, L, PA, PB, s, &qmin, &qmax,
-                                  &n_xcd, &nothing);
-    if (st != HLB_OK || nothing) return st;
-    Plan pl;
-    if ((st = plan(1, k, qmax, std::max<int64_t>(p_absmax, 1), form, &pl)) != HLB_OK) return st;
-    auto_for_shape(&pl, form, m, std::max(nA, nB), k, qmax, std::max<int64_t>(p_absmax, 1));
-    choose_class(&pl, m, std::max(nA, nB), k);
-    std::vector<RightSpec> rights;
-    LeftSpec left{P, ldp, m, {}, {}};
-    for (int l = 0; l < L; ++l) {
-        if (nA > 0) {
-            rights.push_back({A + (int64_t)l * k * nA, nA, nA, primes[l]});
-            left.C.push_back(PA + (int64_t)l * m * nA);
-            left.ldc.push_back(nA);
-        }
-        if (nB > 0) {
-            rights.push_back({B + (int64_t)l * k * nB, nB, nB, primes[l]});
-            left.C.push_back(PB + (int64_t)l * m * nB);
-            left.ldc.push_back(nB);
-        }
-    }
-    return run_products(pl, {left}, rights, k, n_xcd, s);
+    return cp_mm_entry(m, k, nA, nB, P, ldp, p_absmax, A, B, primes, L, PA, PB, form, (hipStream_t)stream);
 }
 
 hlb_status hlb_plan_trunc_b(int64_t k, uint64_t q_min, uint64_t q_max, int64_t p_absmax, double b_err_log2,
@@ -1080,10 +1097,14 @@ hlb_status hlb_validate_residues(const uint64_t *X, int64_t rows, int64_t cols, 
     hlb_status st = device_ready(nullptr);
     if (st != HLB_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    if (stream_capturing(s)) return HLB_EINVAL;  // synchronous: not capturable
     unsigned long long *d = nullptr;
-    if (hipMallocAsync((void **)&d, sizeof(*d), s) != hipSuccess) return HLB_ENOMEM;
+    if (hipMallocAsync((void **)&d, sizeof(*d), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return HLB_ENOMEM;
+    }
     unsigned long long h = ~0ull;
-    if (hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s) != hipSuccess) st = HLB_EDEVICE;
+    if (launch_fill((uint64_t *)d, 1, 1, 1, ~(uint64_t)0, s) != hipSuccess) st = HLB_EDEVICE;
     if (st == HLB_OK && launch_validate(X, rows, cols, ld, q, d, s) != hipSuccess) st = HLB_EDEVICE;
     if (st == HLB_OK && hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) st = HLB_EDEVICE;
     (void)hipFreeAsync(d, s);

@@ -49,14 +49,15 @@ __global__ void absmax_kernel(const int64_t *__restrict__ P, int64_t m, int64_t 
     if (threadIdx.x == 0) atomicMax(out, red[0]);
 }
 
-// Zeros in a rows x cols block of 64-bit words (row stride ld): the outputs of a product over
-// k = 0.  A kernel rather than a memset, so that a caller may capture the call in a graph.
-__global__ void zero_kernel(uint64_t *__restrict__ C, int64_t rows, int64_t cols, int64_t ld) {
+// `value` in a rows x cols block of 64-bit words (row stride ld): zeros for the outputs of a
+// product over k = 0, start values of the reduction counters.  A kernel rather than a memset,
+// so that a caller may capture the call in a graph.
+__global__ void fill_kernel(uint64_t *__restrict__ C, int64_t rows, int64_t cols, int64_t ld, uint64_t value) {
     const int64_t total = rows * cols;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = i / cols, c = i - r * cols;
-        C[r * ld + c] = 0;
+        C[r * ld + c] = value;
     }
 }
 
@@ -131,10 +132,14 @@ hipError_t launch_absmax(const int64_t *P, int64_t m, int64_t k, int64_t ld, uns
     return hipGetLastError();
 }
 
-hipError_t launch_zero(uint64_t *C, int64_t rows, int64_t cols, int64_t ld, hipStream_t s) {
+hipError_t launch_fill(uint64_t *C, int64_t rows, int64_t cols, int64_t ld, uint64_t value, hipStream_t s) {
     if (rows <= 0 || cols <= 0) return hipSuccess;
-    hipLaunchKernelGGL(zero_kernel, dim3(aux_grid(rows * cols)), dim3(kAuxThreads), 0, s, C, rows, cols, ld);
+    hipLaunchKernelGGL(fill_kernel, dim3(aux_grid(rows * cols)), dim3(kAuxThreads), 0, s, C, rows, cols, ld, value);
     return hipGetLastError();
+}
+
+hipError_t launch_zero(uint64_t *C, int64_t rows, int64_t cols, int64_t ld, hipStream_t s) {
+    return launch_fill(C, rows, cols, ld, 0, s);
 }
 
 hipError_t launch_encode(const double *M, int64_t count, double delta, int64_t *out, hipStream_t s) {

@@ -84,6 +84,10 @@ class WsLease {
     void *own_ = nullptr;
     hipStream_t s_ = nullptr;
 };
+// hlb_cp_mm's work (argument checks, plan, products) on stream s.
+hlb_status cp_mm_entry(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp, int64_t p_absmax,
+                       const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L, uint64_t *PA, uint64_t *PB,
+                       int form, hipStream_t s);
 int64_t opt_force_kchunk();
 bool opt_batch_graph();
 void batch_release();

@@ -83,7 +83,9 @@ hipError_t launch_validate(const uint64_t *X, int64_t rows, int64_t cols, int64_
                            unsigned long long *first_bad, hipStream_t s);
 hipError_t launch_absmax(const int64_t *P, int64_t m, int64_t k, int64_t ld,
                          unsigned long long *out, hipStream_t s);
-// Zeros in a rows x cols block of 64-bit words with row stride ld.
+// `value` (launch_fill) or zeros (launch_zero) in a rows x cols block of 64-bit words with row
+// stride ld.
+hipError_t launch_fill(uint64_t *C, int64_t rows, int64_t cols, int64_t ld, uint64_t value, hipStream_t s);
 hipError_t launch_zero(uint64_t *C, int64_t rows, int64_t cols, int64_t ld, hipStream_t s);
 hipError_t launch_encode(const double *M, int64_t count, double delta, int64_t *out, hipStream_t s);
 // D[i] = (sign * AS[i] + E[i]) mod q elementwise over `count` entries, with AS residues and

@@ -94,3 +94,42 @@ def test_caller_captures_cp_mm_in_a_graph(form):
         g.replay()
         assert np.array_equal(_np(PA), want[0]) and np.array_equal(_np(PB), want[1])
         torch.randn(1000, device=DEV).sum().item()
+
+
+def test_capture_with_measured_bound_is_refused_before_any_enqueue():
+    # p_absmax = 0 asks the library to measure max |P| on the device, which needs a copy to the
+    # host and a synchronization: on a capturing stream the call must fail with HLB_EINVAL
+    # before it enqueues anything, leaving the capture intact (the graph then holds only the
+    # caller's own work and replays it).
+    w, want = _case(61, (120, 300, 96, 2))
+    P, A, B = _t(w.P), _t(w.A), _t(w.B)
+    PA = torch.empty((2, 120, 96), dtype=torch.int64, device=DEV)
+    PB = torch.empty_like(PA)
+    flag = torch.zeros(4, dtype=torch.int64, device=DEV)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    status = {}
+    with torch.cuda.graph(g, stream=s):
+        flag.add_(1)
+        for name, fn in (("cp_mm", lambda: hlb.cp_mm(P, A, B, w.primes, p_absmax=0, form="int8_crt",
+                                                       out=(PA, PB), stream=s)),
+                         ("absmax", lambda: hlb.plaintext_absmax(P, stream=s)),
+                         ("validate", lambda: hlb.validate_residues(A[0], w.primes[0], stream=s)),
+                         ("batch", lambda: hlb.cp_mm_batch([dict(P=P, A=A, B=B, p_absmax=0, PA=PA, PB=PB)],
+                                                           w.primes, form="int8_crt", stream=s))):
+            try:
+                fn()
+                status[name] = 0
+            except hlb.HlbError as e:
+                status[name] = e.status
+        flag.add_(1)
+    assert status == {"cp_mm": 1, "absmax": 1, "validate": 1, "batch": 1}, status
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        assert flag.tolist() == [2 * (rep + 1)] * 4
+    # the same call outside capture measures the bound and is exact
+    PA2, PB2 = hlb.cp_mm(P, A, B, w.primes, p_absmax=0, form="int8_crt")
+    assert np.array_equal(_np(PA2), want[0]) and np.array_equal(_np(PB2), want[1])
