@@ -135,11 +135,39 @@ def _stream(stream=None) -> int:
     return s.cuda_stream
 
 
-def _dev64(t: torch.Tensor, name: str) -> torch.Tensor:
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError(f"{name} must be a CUDA tensor")
+def _int64(t, name: str) -> torch.Tensor:
+    """A 64-bit integer tensor (int64 or uint64; residues < 2^52 are bit-identical in both)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
     if t.dtype not in (torch.int64, torch.uint64):
         raise TypeError(f"{name} must be int64 or uint64, got {t.dtype}")
+    return t
+
+
+def _shape(t, name: str, shape) -> torch.Tensor:
+    """Checks dtype and exact shape (ValueError on a shape mismatch) -- no device access."""
+    _int64(t, name)
+    if tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _on_device(ref: torch.Tensor, *named) -> None:
+    """Every tensor must live on the same CUDA device as `ref` (checked after the shapes, so
+    that shape errors are reported before anything touches a device)."""
+    if not ref.is_cuda:
+        raise TypeError("operands must be CUDA tensors")
+    for t, name in named:
+        if not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if t.device != ref.device:
+            raise ValueError(f"{name} is on {t.device}, the operands on {ref.device}")
+
+
+def _dev64(t: torch.Tensor, name: str) -> torch.Tensor:
+    _int64(t, name)
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
     return t
 
 
@@ -157,14 +185,18 @@ def _row_stride(t: torch.Tensor, name: str) -> int:
 
 def hlb_mod_pp_mm(q: int, P: torch.Tensor, X: torch.Tensor, form="auto", out=None, stream=None):
     """C = P X mod q (Mod-PP-MM).  P: m x k residues, X: k x n residues; returns m x n."""
-    _dev64(P, "P")
-    _dev64(X, "X")
+    _int64(P, "P")
+    _int64(X, "X")
+    if P.dim() != 2 or X.dim() != 2:
+        raise ValueError("P and X must be 2-D")
     m, k = P.shape
     k2, n = X.shape
     if k != k2:
         raise ValueError("inner dimensions differ")
+    if out is not None:
+        _shape(out, "out", (m, n))
+    _on_device(P, (X, "X"), *(((out, "out"),) if out is not None else ()))
     C = out if out is not None else torch.empty((m, n), dtype=torch.int64, device=P.device)
-    _dev64(C, "out")
     _check(load().hlb_mod_pp_mm(int(q), m, k, n, P.data_ptr(), _row_stride(P, "P"), X.data_ptr(),
                                 _row_stride(X, "X"), C.data_ptr(), _row_stride(C, "out"),
                                 _form(form), _stream(stream)), "mod_pp_mm")
@@ -172,24 +204,29 @@ def hlb_mod_pp_mm(q: int, P: torch.Tensor, X: torch.Tensor, form="auto", out=Non
 
 
 def _cp_mm_operands(P, A, B, primes, out):
-    _dev64(P, "P")
-    _dev64(A, "A")
-    _dev64(B, "B")
+    _int64(P, "P")
+    _int64(A, "A")
+    _int64(B, "B")
     L = len(primes)
+    if P.dim() != 2:
+        raise ValueError("P must be 2-D (m x k)")
     m, k = P.shape
     if A.dim() != 3 or B.dim() != 3 or A.shape[0] != L or B.shape[0] != L or A.shape[1] != k \
             or B.shape[1] != k:
         raise ValueError("A and B must be [L, k, n] with L = len(primes)")
+    nA, nB = A.shape[2], B.shape[2]
+    if out is not None:
+        PA, PB = out
+        _shape(PA, "PA", (L, m, nA))
+        _shape(PB, "PB", (L, m, nB))
+    _on_device(P, (A, "A"), (B, "B"), *(((PA, "PA"), (PB, "PB")) if out is not None else ()))
     if not (A.is_contiguous() and B.is_contiguous()):
         raise ValueError("A and B must be contiguous")
-    nA, nB = A.shape[2], B.shape[2]
     if out is None:
         PA = torch.empty((L, m, nA), dtype=torch.int64, device=P.device)
         PB = torch.empty((L, m, nB), dtype=torch.int64, device=P.device)
-    else:
-        PA, PB = out
-        if not (PA.is_contiguous() and PB.is_contiguous()):
-            raise ValueError("outputs must be contiguous")
+    elif not (PA.is_contiguous() and PB.is_contiguous()):
+        raise ValueError("outputs must be contiguous")
     qs = (ctypes.c_uint64 * max(L, 1))(*[int(q) for q in primes])
     return (m, k, nA, nB, P.data_ptr(), _row_stride(P, "P")), (A.data_ptr(), B.data_ptr(), qs, L,
                                                               PA.data_ptr(), PB.data_ptr()), PA, PB
@@ -233,10 +270,27 @@ def hlb_cp_mm_batch(problems, primes: Sequence[int], form="int8", stream=None):
     allocated when absent).  Returns the list of (PA, PB).
     """
     L = len(primes)
+    # shapes of every problem first, then devices: a bad member fails before any allocation
+    ref = None
+    for i, pr in enumerate(problems):
+        P, A, B = _int64(pr["P"], f"P[{i}]"), _int64(pr["A"], f"A[{i}]"), _int64(pr["B"], f"B[{i}]")
+        if P.dim() != 2:
+            raise ValueError(f"P of problem {i} must be 2-D (m x k)")
+        m, k = P.shape
+        if A.dim() != 3 or B.dim() != 3 or tuple(A.shape[:2]) != (L, k) or tuple(B.shape[:2]) != (L, k):
+            raise ValueError(f"A and B of problem {i} must be [L, k, n] with L = len(primes), k = {k}")
+        if pr.get("PA") is not None:
+            _shape(pr["PA"], f"PA[{i}]", (L, m, A.shape[2]))
+        if pr.get("PB") is not None:
+            _shape(pr["PB"], f"PB[{i}]", (L, m, B.shape[2]))
+        ref = P if ref is None else ref
+    for i, pr in enumerate(problems):
+        _on_device(ref, *((pr[key], f"{key}[{i}]") for key in ("P", "A", "B", "PA", "PB")
+                          if pr.get(key) is not None))
     arr = (CpmmProblem * max(len(problems), 1))()
     outs = []
     for i, pr in enumerate(problems):
-        P, A, B = _dev64(pr["P"], "P"), _dev64(pr["A"], "A"), _dev64(pr["B"], "B")
+        P, A, B = pr["P"], pr["A"], pr["B"]
         m, k = P.shape
         nA, nB = A.shape[2], B.shape[2]
         PA = pr.get("PA")
@@ -262,14 +316,18 @@ def hlb_ccmm_pp_core(A, B, At, Bt, primes: Sequence[int], form="auto", stream=No
     """[A; B] * [At Bt] modulo each prime (CC-MM plaintext core): returns (C00, C01, C10, C11),
     each [L, m, n].  A, B: [L, m, k]; At, Bt: [L, k, n]; all contiguous residue tensors."""
     for t, nm in ((A, "A"), (B, "B"), (At, "At"), (Bt, "Bt")):
-        _dev64(t, nm)
-        if t.dim() != 3 or not t.is_contiguous():
+        _int64(t, nm)
+        if t.dim() != 3:
             raise ValueError(f"{nm} must be a contiguous [L, rows, cols] tensor")
     L = len(primes)
     _, m, k = A.shape
     n = At.shape[2]
     if B.shape != A.shape or Bt.shape != At.shape or At.shape[1] != k or A.shape[0] != L or At.shape[0] != L:
         raise ValueError("shapes must be A, B: [L, m, k] and At, Bt: [L, k, n]")
+    _on_device(A, (B, "B"), (At, "At"), (Bt, "Bt"))
+    for t, nm in ((A, "A"), (B, "B"), (At, "At"), (Bt, "Bt")):
+        if not t.is_contiguous():
+            raise ValueError(f"{nm} must be a contiguous [L, rows, cols] tensor")
     outs = [torch.empty((L, m, n), dtype=torch.int64, device=A.device) for _ in range(4)]
     qs = (ctypes.c_uint64 * max(L, 1))(*[int(q) for q in primes])
     _check(load().hlb_ccmm_pp_core(m, k, n, A.data_ptr(), B.data_ptr(), At.data_ptr(), Bt.data_ptr(), qs, L,
@@ -367,7 +425,16 @@ def hlb_test_encode(M: torch.Tensor, delta: float, stream=None) -> torch.Tensor:
 
 
 def hlb_test_encrypt(A: torch.Tensor, S: torch.Tensor, Menc: torch.Tensor, primes, stream=None):
+    _int64(A, "A")
+    if A.dim() != 3 or A.shape[0] != len(primes):
+        raise ValueError("A must be [L, k, n] with L = len(primes)")
     L, k, n = A.shape
+    _shape(S, "S", (n, n))
+    _shape(Menc, "Menc", (k, n))
+    _on_device(A, (S, "S"), (Menc, "Menc"))
+    for t, nm in ((A, "A"), (S, "S"), (Menc, "Menc")):
+        if not t.is_contiguous():
+            raise ValueError(f"{nm} must be contiguous")
     B = torch.empty_like(A)
     qs = (ctypes.c_uint64 * max(L, 1))(*[int(q) for q in primes])
     _check(load().hlb_test_encrypt(k, n, A.data_ptr(), S.data_ptr(), Menc.data_ptr(), qs, L,
@@ -376,7 +443,16 @@ def hlb_test_encrypt(A: torch.Tensor, S: torch.Tensor, Menc: torch.Tensor, prime
 
 
 def hlb_test_decrypt(A: torch.Tensor, B: torch.Tensor, S: torch.Tensor, primes, stream=None):
+    _int64(A, "A")
+    if A.dim() != 3 or A.shape[0] != len(primes):
+        raise ValueError("A must be [L, rows, n] with L = len(primes)")
     L, rows, n = A.shape
+    _shape(B, "B", tuple(A.shape))
+    _shape(S, "S", (n, n))
+    _on_device(A, (B, "B"), (S, "S"))
+    for t, nm in ((A, "A"), (B, "B"), (S, "S")):
+        if not t.is_contiguous():
+            raise ValueError(f"{nm} must be contiguous")
     D = torch.empty_like(A)
     qs = (ctypes.c_uint64 * max(L, 1))(*[int(q) for q in primes])
     _check(load().hlb_test_decrypt(rows, n, A.data_ptr(), B.data_ptr(), S.data_ptr(), qs, L,

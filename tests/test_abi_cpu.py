@@ -244,3 +244,62 @@ def test_crt_plan_moduli_count():
         assert p["form"] == 3 and p["p_limbs"] == D
     with pytest.raises(hlb.HlbError):
         hlb.plan(1, 131072, Q50, 1 << 20, "int8_crt")
+
+
+def test_binding_rejects_mismatched_tensors_before_device_work():
+    # Shapes are checked before devices, so CPU (and meta) tensors of the wrong shape raise
+    # ValueError without any device call; correctly shaped CPU tensors then raise TypeError
+    # (they are not device memory) instead of reaching the library.
+    import torch
+
+    def z(*shape, dtype=torch.int64):
+        return torch.zeros(shape, dtype=dtype, device="meta")
+
+    q = [Q50, Q50 - 2]
+    L, m, k, n = 2, 8, 6, 5
+    P, A, B = z(m, k), z(L, k, n), z(L, k, n)
+    # undersized, transposed or wrongly batched outputs of cp_mm / cp_mm_trunc_b
+    for PA, PB in [(z(L, m, n - 1), z(L, m, n)), (z(L, m, n), z(L, m - 1, n)), (z(1, m, n), z(L, m, n)),
+                   (z(L, n, m), z(L, m, n)), (z(L * m * n), z(L, m, n))]:
+        with pytest.raises(ValueError):
+            hlb.cp_mm(P, A, B, q, p_absmax=1, out=(PA, PB))
+    for PA, PB in [(z(1, m, n - 1), z(1, m, n)), (z(1, m, n), z(1, m + 1, n)), (z(2, m, n), z(1, m, n))]:
+        with pytest.raises(ValueError):
+            hlb.cp_mm_trunc_b(P, A[:1], B[:1], [Q50], 40.0, p_absmax=1, out=(PA, PB))
+    # short or mis-sized ciphertext parts
+    with pytest.raises(ValueError):
+        hlb.cp_mm(P, z(L, k - 1, n), B, q)
+    with pytest.raises(ValueError):
+        hlb.cp_mm(P, A, z(L + 1, k, n), q)
+    with pytest.raises(ValueError):
+        hlb.cp_mm(z(m * k), A, B, q)
+    # wrong dtype is a TypeError
+    with pytest.raises(TypeError):
+        hlb.cp_mm(P, A, B, q, out=(z(L, m, n, dtype=torch.int32), z(L, m, n)))
+    # mod_pp_mm: out must be m x n
+    with pytest.raises(ValueError):
+        hlb.mod_pp_mm(Q50, z(m, k), z(k, n), out=z(m, n + 1))
+    with pytest.raises(ValueError):
+        hlb.mod_pp_mm(Q50, z(m, k), z(k + 1, n))
+    # batch: every member's A, B, PA, PB against its P and the prime count
+    good = dict(P=P, A=A, B=B)
+    for bad in [dict(P=P, A=z(L, k + 1, n), B=B), dict(P=P, A=A, B=z(L, k, n)[0]),
+                dict(P=P, A=z(L + 1, k, n), B=B), dict(P=P, A=A, B=B, PA=z(L, m - 1, n)),
+                dict(P=P, A=A, B=B, PB=z(L, m, n + 3)), dict(P=z(m, k, 1), A=A, B=B)]:
+        with pytest.raises(ValueError):
+            hlb.cp_mm_batch([good, bad], q)
+    # ccmm core and the test helpers
+    with pytest.raises(ValueError):
+        hlb.ccmm_pp_core(z(L, m, k), z(L, m, k), z(L, k, n), z(L, k + 1, n), q)
+    with pytest.raises(ValueError):
+        hlb.hlb_test_encrypt(z(L, k, n), z(n, n - 1), z(k, n), q)
+    with pytest.raises(ValueError):
+        hlb.hlb_test_encrypt(z(L, k, n), z(n, n), z(k - 1, n), q)
+    with pytest.raises(ValueError):
+        hlb.hlb_test_decrypt(z(L, m, n), z(L, m - 1, n), z(n, n), q)
+    # correct shapes on the CPU: refused as non-device tensors, never passed to the library
+    c = lambda *s: torch.zeros(s, dtype=torch.int64)
+    with pytest.raises(TypeError):
+        hlb.cp_mm(c(m, k), c(L, k, n), c(L, k, n), q, out=(c(L, m, n), c(L, m, n)))
+    with pytest.raises(TypeError):
+        hlb.cp_mm_batch([dict(P=c(m, k), A=c(L, k, n), B=c(L, k, n))], q)
