@@ -55,7 +55,9 @@ typedef enum {
     HLB_EBOUND = 3,  /* no exact limb plan exists for this form, shape and input bound */
     HLB_ENOMEM = 4,  /* device workspace allocation failed */
     HLB_EDEVICE = 5, /* a HIP runtime call or kernel launch failed */
-    HLB_EUNSUP = 6   /* device is not gfx950, or the requested option is unknown */
+    HLB_EUNSUP = 6,  /* device is not gfx950, or the requested option is unknown */
+    HLB_ESCRATCH = 7 /* hlb_cp_mm_noalloc: the call needs more workspace than its static
+                        scratch buffer holds (HLB_NOALLOC_SCRATCH_BYTES) */
 } hlb_status;
 
 typedef enum {
@@ -101,6 +103,28 @@ hlb_status hlb_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB,
                      const int64_t *P, int64_t ldp, int64_t p_absmax,
                      const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L,
                      uint64_t *PA, uint64_t *PB, int form, void *stream);
+
+/*
+ * hlb_cp_mm for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  Same arguments, results and forms
+ * as hlb_cp_mm, bit-identical to it, with two differences:
+ *   - Every workspace buffer (operand planes, multimodular product bytes, FP64 planes) is
+ *     carved from one static device array of HLB_NOALLOC_SCRATCH_BYTES, which each device the
+ *     library runs on holds from the library's first use there until the process ends.  The
+ *     call allocates and frees nothing.  A call whose workspace exceeds the array returns
+ *     HLB_ESCRATCH before anything is enqueued (about d = 1024 over 3 primes fits in every
+ *     form; hlb_cp_mm has no such limit).
+ *   - p_absmax must be given (>= 1): measuring it would allocate (HLB_EINVAL for 0).
+ * The array is shared by every hlb_cp_mm_noalloc call on a device and keeps the last call's
+ * contents (nothing in it needs clearing: every call writes all the bytes it reads).  Calls
+ * on one stream run in stream order; calls that overlap on one device (different streams,
+ * concurrent graph replays) race on the array and must be ordered by the caller.
+ */
+#define HLB_NOALLOC_SCRATCH_BYTES ((uint64_t)256 << 20)
+hlb_status hlb_cp_mm_noalloc(int64_t m, int64_t k, int64_t nA, int64_t nB,
+                             const int64_t *P, int64_t ldp, int64_t p_absmax,
+                             const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L,
+                             uint64_t *PA, uint64_t *PB, int form, void *stream);
 
 /*
  * CP-MM with an approximate b-part (Strategy 2 of Section 6.1, "truncation") over ONE

@@ -20,12 +20,12 @@ import torch
 
 __all__ = [
     "HlbError", "FORM_AUTO", "FORM_FP64", "FORM_INT8", "library_path", "load",
-    "hlb_mod_pp_mm", "hlb_cp_mm", "hlb_cp_mm_batch", "hlb_validate_residues",
+    "hlb_mod_pp_mm", "hlb_cp_mm", "hlb_cp_mm_noalloc", "hlb_cp_mm_batch", "hlb_validate_residues",
     "hlb_plaintext_absmax", "hlb_plan", "hlb_set_option", "hlb_profile_read",
     "hlb_profile_reset", "hlb_release", "hlb_status_str", "hlb_test_encode",
     "hlb_test_encrypt", "hlb_test_decrypt", "hlb_tune_set", "hlb_tune_load", "hlb_tune_class",
     "hlb_ccmm_pp_core", "hlb_rescale", "ccmm_pp_core", "rescale",
-    "mod_pp_mm", "cp_mm", "cp_mm_batch", "validate_residues", "plaintext_absmax", "plan",
+    "mod_pp_mm", "cp_mm", "cp_mm_noalloc", "cp_mm_batch", "validate_residues", "plaintext_absmax", "plan",
     "set_option", "profile_read", "profile_reset", "release",
 ]
 
@@ -33,6 +33,7 @@ FORM_AUTO, FORM_FP64, FORM_INT8, FORM_INT8_CRT = 0, 1, 2, 3
 _FORMS = {"auto": FORM_AUTO, "fp64": FORM_FP64, "int8": FORM_INT8, "int8_crt": FORM_INT8_CRT}
 OPT_FORCE_KCHUNK, OPT_PROFILE, OPT_BATCH_GRAPH, OPT_FORCE_CLASS, OPT_F64_PLANES, OPT_CRT_WIDE = 1, 2, 3, 4, 5, 6
 OPT_WS_CAP = 7
+NOALLOC_SCRATCH_BYTES = 256 << 20   # HLB_NOALLOC_SCRATCH_BYTES
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libhlb.so")
@@ -87,6 +88,7 @@ def load():
             "hlb_status_str": (ctypes.c_char_p, [ci]),
             "hlb_mod_pp_mm": (ci, [u64, i64, i64, i64, vp, i64, vp, i64, vp, i64, ci, vp]),
             "hlb_cp_mm": (ci, [i64, i64, i64, i64, vp, i64, i64, vp, vp, vp, ci, vp, vp, ci, vp]),
+            "hlb_cp_mm_noalloc": (ci, [i64, i64, i64, i64, vp, i64, i64, vp, vp, vp, ci, vp, vp, ci, vp]),
             "hlb_cp_mm_trunc_b": (ci, [i64, i64, i64, i64, vp, i64, i64, vp, vp, vp, ci, vp, vp,
                                        ctypes.c_double, ci, vp]),
             "hlb_plan_trunc_b": (ci, [i64, u64, u64, i64, ctypes.c_double, ci, vp]),
@@ -241,6 +243,17 @@ def hlb_cp_mm(P: torch.Tensor, A: torch.Tensor, B: torch.Tensor, primes: Sequenc
     """
     head, tail, PA, PB = _cp_mm_operands(P, A, B, primes, out)
     _check(load().hlb_cp_mm(*head, int(p_absmax), *tail, _form(form), _stream(stream)), "cp_mm")
+    return PA, PB
+
+
+def hlb_cp_mm_noalloc(P: torch.Tensor, A: torch.Tensor, B: torch.Tensor, primes: Sequence[int],
+                      p_absmax: int, form="int8", out=None, stream=None):
+    """hlb_cp_mm with every workspace buffer in the library's static scratch array (no device
+    allocation in the library; HLB_NOALLOC_SCRATCH_BYTES per device).  p_absmax must be >= 1.
+    Pass `out` to keep the call itself allocation-free (otherwise the outputs are allocated
+    here, by torch, before the call)."""
+    head, tail, PA, PB = _cp_mm_operands(P, A, B, primes, out)
+    _check(load().hlb_cp_mm_noalloc(*head, int(p_absmax), *tail, _form(form), _stream(stream)), "cp_mm_noalloc")
     return PA, PB
 
 
@@ -466,6 +479,7 @@ rescale = hlb_rescale
 mod_pp_mm = hlb_mod_pp_mm
 cp_mm = hlb_cp_mm
 cp_mm_trunc_b = hlb_cp_mm_trunc_b
+cp_mm_noalloc = hlb_cp_mm_noalloc
 plan_trunc_b = hlb_plan_trunc_b
 cp_mm_batch = hlb_cp_mm_batch
 validate_residues = hlb_validate_residues

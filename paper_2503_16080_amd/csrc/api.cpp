@@ -430,8 +430,18 @@ static std::map<std::pair<int, hipStream_t>, WsSlot *> g_slots;
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// The calling thread's scratch span while a ScratchScope is alive (the no-allocation entry
+// point): the lease then carves its buffers from the span and allocates nothing.
+static thread_local const ScratchScope *t_scratch = nullptr;
+
+ScratchScope::ScratchScope(void *base, size_t bytes) : base_(base), bytes_(bytes), prev_(t_scratch) {
+    t_scratch = this;
+}
+ScratchScope::~ScratchScope() { t_scratch = prev_; }
+
 hlb_status WsLease::take(hipStream_t s, const size_t *bytes, void **ptrs, int n) {
-    const int64_t cap = g_ws_cap.load();
+    const ScratchScope *scr = t_scratch;
+    const int64_t cap = scr ? 0 : g_ws_cap.load();
     size_t total = 0;
     for (int i = 0; i < n; ++i) {
         ptrs[i] = nullptr;
@@ -443,7 +453,10 @@ hlb_status WsLease::take(hipStream_t s, const size_t *bytes, void **ptrs, int n)
     s_ = s;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     char *base = nullptr;
-    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+    if (scr) {
+        if (total > scr->bytes()) return HLB_ESCRATCH;
+        base = (char *)scr->base();
+    } else if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
         if (hipMallocAsync(&own_, total, s) != hipSuccess) {
             (void)hipGetLastError();
             own_ = nullptr;
@@ -911,6 +924,7 @@ const char *hlb_status_str(int s) {
         case HLB_ENOMEM: return "device workspace allocation failed";
         case HLB_EDEVICE: return "HIP runtime or kernel launch failure";
         case HLB_EUNSUP: return "unsupported device or option";
+        case HLB_ESCRATCH: return "workspace exceeds the no-allocation scratch buffer";
         default: return "unknown status";
     }
 }

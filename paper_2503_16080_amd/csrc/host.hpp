@@ -84,6 +84,23 @@ class WsLease {
     void *own_ = nullptr;
     hipStream_t s_ = nullptr;
 };
+// While alive, WsLease::take on this thread carves every workspace from [base, base + bytes)
+// instead of allocating, and returns HLB_ESCRATCH when a call needs more.
+class ScratchScope {
+  public:
+    ScratchScope(void *base, size_t bytes);
+    ~ScratchScope();
+    ScratchScope(const ScratchScope &) = delete;
+    ScratchScope &operator=(const ScratchScope &) = delete;
+    void *base() const { return base_; }
+    size_t bytes() const { return bytes_; }
+
+  private:
+    void *base_;
+    size_t bytes_;
+    const ScratchScope *prev_;
+};
+
 // hlb_cp_mm's work (argument checks, plan, products) on stream s.
 hlb_status cp_mm_entry(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp, int64_t p_absmax,
                        const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L, uint64_t *PA, uint64_t *PB,
