@@ -11,9 +11,13 @@ GEMM launch over all 11 moduli x 6 products, and one recombination per output ma
 Also reported: the INT8 digit form (Strategy 1, 3 x 7 digit products), the FP64-limb form,
 a same-shape vendor FP64 GEMM (torch float64 matmul, d^3) and the resulting slowdowns, each
 GEMM's roofline position (HIP events around its launches, inside the timed region), and the
-CPU oracle's rate on a bounded row sample.
+CPU oracle's rate on a bounded row sample.  The same line carries one key per other workload,
+each with its own roofline block: the CP-MM at d = 4096 over 3 primes in the FP64-limb form,
+the CP-MM at d = 16384 over 2 primes in the multimodular form, and the batch of 64 uneven
+CP-MMs over 4 primes of 45 bits (graph-replayed batch call, against per-product loops).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-extra-configs] [--workload cpmm|batch|trunc]
 """
 from __future__ import annotations
 
@@ -43,6 +47,11 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-limb and dgemm legs")
     ap.add_argument("--no-digit", action="store_true", help="skip the digit (Strategy 1) INT8 leg")
+    ap.add_argument("--no-batch-loops", action="store_true",
+                    help="batch workload: skip the per-product launch loops")
+    ap.add_argument("--no-extra-configs", action="store_true",
+                    help="skip the legs of the other workloads: d = 4096 FP64 form, d = 16384 over 2 "
+                         "primes, and the 64-problem batch")
     ap.add_argument("--workload", choices=["cpmm", "batch", "trunc"], default="cpmm",
                     help="cpmm: one CP-MM of size --d (default); batch: 64 CP-MMs of uneven "
                          "shapes over 4 primes of 45 bits; trunc: the CP-MM of size --d with "
@@ -55,6 +64,9 @@ def _parse():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the counter summary from two rocprofv3 --pmc output directories "
                          "(FETCH_SIZE run, WRITE_SIZE run) and exit")
+    ap.add_argument("--summarize-mfma", metavar="PMC_DIR",
+                    help="write the matrix-pipe summary of each GEMM kernel from one rocprofv3 --pmc "
+                         "run of SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run 3 device-to-device copies of 1 GiB (a reference kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -69,11 +81,16 @@ TRAFFIC = {
                  "match": "crt_gemm_kernel"},
     "gemm_i8": {"sources": [os.path.join(_CSRC, f) for f in ("gemm_i8.hip", "i8_tile.hpp", "common.hpp")],
                 "match": "gemm_i8_kernel"},
+    "gemm_f64": {"sources": [os.path.join(_CSRC, f) for f in ("gemm_f64_planes.hip", "common.hpp")],
+                 "match": "gemm_f64_planes_kernel"},
+    "crt_gemm_batch": {"sources": [os.path.join(_CSRC, f) for f in ("crt.hip", "crt.hpp", "common.hpp", "batch.hip")],
+                       "match": "crt_gemm_batch_kernel"},
 }
 
 
 def traffic_file(kernel, d, L):
-    """The counter summary of `kernel` on the CP-MM of size d over L primes."""
+    """The counter summary of `kernel` on the CP-MM of size d over L primes (d = "batch64":
+    the 64-problem batch)."""
     name = f"{kernel}_traffic.json" if (d, L) == (8192, 3) else f"{kernel}_traffic_d{d}_L{L}.json"
     return os.path.join(ROOT, "profiles", name)
 
@@ -101,6 +118,55 @@ def measured_traffic(kernel, d, L):
     return t["fetch_kib"] * 1024 * t["fetch_scale"] + t["write_kib"] * 1024 * t["write_scale"]
 
 
+def mfma_file(kernel, d, L):
+    return os.path.join(ROOT, "profiles", f"{kernel}_mfma_d{d}_L{L}.json")
+
+
+def measured_mfma(kernel, d, L):
+    """Matrix-pipe occupancy of `kernel` from its committed counter summary (busy fraction of
+    the SIMD cycles and the clock it ran at), or None when missing or stale."""
+    try:
+        with open(mfma_file(kernel, d, L)) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash(kernel) or t.get("d") != d or t.get("primes") != L:
+        return None
+    return {"busy_frac": t["mfma_busy_frac"], "clock_ghz": t["clock_ghz"]}
+
+
+def summarize_mfma(pmc_dir, d, L, kernel, simds=1024, xcds=8):
+    """Turns one rocprofv3 --pmc run of SQ_VALU_MFMA_BUSY_CYCLES, SQ_BUSY_CYCLES and
+    GRBM_GUI_ACTIVE into the matrix-pipe summary of `kernel`: SQ_VALU_MFMA_BUSY_CYCLES counts
+    busy cycles summed over all SIMDs, GRBM_GUI_ACTIVE active cycles summed over the XCDs, so
+    busy_frac = MFMA cycles / (SIMDs x cycles per XCD) and clock = cycles per XCD / duration."""
+    import csv
+    import glob
+    import statistics
+    (name,) = glob.glob(os.path.join(pmc_dir, "*counter_collection.csv"))
+    vals, durs = {}, []
+    for r in csv.DictReader(open(name)):
+        if TRAFFIC[kernel]["match"] not in r["Kernel_Name"]:
+            continue
+        vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        if r["Counter_Name"] == "GRBM_GUI_ACTIVE":
+            durs.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    if "SQ_VALU_MFMA_BUSY_CYCLES" not in vals or "GRBM_GUI_ACTIVE" not in vals:
+        return None
+    mfma = statistics.mean(vals["SQ_VALU_MFMA_BUSY_CYCLES"])
+    cycles = statistics.mean(vals["GRBM_GUI_ACTIVE"]) / xcds
+    out = {"kernel": kernel, "kernel_source_sha256": kernel_source_hash(kernel), "d": d, "primes": L,
+           "dispatches": len(durs), "SQ_VALU_MFMA_BUSY_CYCLES": mfma,
+           "GRBM_GUI_ACTIVE": statistics.mean(vals["GRBM_GUI_ACTIVE"]),
+           "SQ_BUSY_CYCLES": statistics.mean(vals.get("SQ_BUSY_CYCLES", [0.0])),
+           "duration_s": statistics.mean(durs), "simds": simds, "xcds": xcds,
+           "mfma_busy_frac": mfma / (simds * cycles), "clock_ghz": cycles / statistics.mean(durs) / 1e9}
+    with open(mfma_file(kernel, d, L), "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    return out
+
+
 def summarize_counters(fetch_dir, write_dir, d, L, kernel):
     """Turns two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, each with
     --copy-calibration) into the counter summary of `kernel`: per-dispatch KiB and the scale
@@ -116,10 +182,12 @@ def summarize_counters(fetch_dir, write_dir, d, L, kernel):
                 if r["Counter_Name"] == counter and TRAFFIC[kernel]["match"] in r["Kernel_Name"]]
         copy = [float(r["Counter_Value"]) for r in rows
                 if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]]
-        return statistics.mean(gemm), statistics.mean(copy)
+        return (statistics.mean(gemm) if gemm else None), statistics.mean(copy)
 
     fetch, fcopy = per_kernel(fetch_dir, "FETCH_SIZE")
     write, wcopy = per_kernel(write_dir, "WRITE_SIZE")
+    if fetch is None or write is None:
+        return None  # the kernel did not run in these traces
     gib_kib = float(1 << 20)
     out = {"kernel": kernel, "kernel_source_sha256": kernel_source_hash(kernel), "d": d, "primes": L,
            "fetch_kib": fetch, "write_kib": write,
@@ -143,6 +211,18 @@ def _time_steps(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu's "Model name", read from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, target_s=15.0):
     """The oracle timed on a bounded row sample of the same CP-MM (all primes, both parts)."""
     import oracle
@@ -157,35 +237,64 @@ def cpu_baseline(w, target_s=15.0):
     oracle.cp_mm(w.P, w.A, w.B, w.primes, rows=sample)
     dt = time.perf_counter() - t0
     return {"value": len(sample) * per_row / dt, "unit": "mod-q MAC/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": oracle.num_threads(), "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"{len(sample)} of {m} output rows of the CP-MM (all {L} primes, a- and "
                       f"b-parts), {dt:.1f} s; rate scales linearly with rows"}
 
 
-def run_batch(args):
+def _roofline(kernel, launches, ms, ops_per_step, steps, d, L, peak, unit, op, bound="mfma"):
+    """Roofline block of a kernel timed with HIP events on its launch stream: the algorithmic
+    work of one launch (the step's work over its launches of the kernel) over the launch's
+    average duration, against the type's dense peak; `traffic` is the committed counter
+    summary's HBM bytes per launch when it matches the kernel's current sources."""
+    per_step = launches / steps
+    ops = ops_per_step / per_step
+    rate = ops / (ms * 1e-3) / 1e12
+    traffic = measured_traffic(kernel, d, L)
+    return {"bound": bound, "achieved": rate, "peak": peak, "unit": unit,
+            "frac": rate / peak, "traffic": traffic,
+            "traffic_gbs": None if traffic is None else traffic / (ms * 1e-3) / 1e9,
+            "mfma_counters": measured_mfma(kernel, d, L),
+            "kernel": TRAFFIC[kernel]["match"], "avg_launch_ms": ms, "launches": launches,
+            "launches_per_step": per_step, "ops_per_launch": ops, "op": op}
+
+
+def _profiled(fn, names, steps, warmup):
+    """Step time of fn with the library's kernels bracketed by HIP events on their launch
+    stream; returns (seconds per step, {name: (launches, average ms)})."""
+    import paper_2503_16080_amd as hlb
+    for _ in range(warmup):
+        fn()
+    import torch
+    torch.cuda.synchronize()
+    hlb.profile_reset()
+    hlb.set_option(hlb.OPT_PROFILE, 1)
+    s = _time_steps(fn, steps, 0)
+    hlb.set_option(hlb.OPT_PROFILE, 0)
+    prof = {n: hlb.profile_read(n) for n in names}
+    hlb.profile_reset()
+    return s, {n: (c, t / max(c, 1)) for n, (c, t) in prof.items()}
+
+
+def batch_leg(steps, warmup, loops=True):
     """64 independent CP-MMs with d log-uniform in [128, 4096], m log-uniform in [64, 4096],
-    n = d, over 4 primes of 45 bits, as one batch call: the multimodular form (batched residue
-    splits, one GEMM launch, batched recombination) and the digit form (one persistent
-    launch), both graph-replayed, against per-product loops of hlb_cp_mm calls."""
+    n = d, over 4 primes of 45 bits (inputs drawn on the device), as one batch call: the
+    multimodular form (batched residue splits, one GEMM launch, batched recombination) and the
+    digit form (one persistent launch), both graph-replayed, against per-product loops of
+    hlb_cp_mm calls.  The GEMM's roofline comes from the same batch launched eagerly (the
+    kernels of a replayed graph cannot be bracketed by events)."""
     import torch
 
     import paper_2503_16080_amd as hlb
     import workloads as wl
 
     seed, L, bits = 1004, 4, 45
-    shapes = wl.batch_shapes(seed, 64)
-    primes = wl.ntt_primes(bits, L, skip=seed % 8)
+    primes, shapes, probs = wl.batch_problems_device(seed, 64, bits, L)
     dev = torch.device("cuda:0")
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(seed)
-    probs, macs = [], 0
-    for (m, d) in shapes:
-        P = torch.randint(-(1 << 20), (1 << 20) + 1, (m, d), dtype=torch.int64, device=dev, generator=gen)
-        A = torch.stack([torch.randint(0, q, (d, d), dtype=torch.int64, device=dev, generator=gen) for q in primes])
-        B = torch.stack([torch.randint(0, q, (d, d), dtype=torch.int64, device=dev, generator=gen) for q in primes])
-        probs.append(dict(P=P, A=A, B=B, p_absmax=1 << 20,
-                          PA=torch.empty((L, m, d), dtype=torch.int64, device=dev),
-                          PB=torch.empty((L, m, d), dtype=torch.int64, device=dev)))
+    macs = 0
+    for p, (m, d) in zip(probs, shapes):
+        p["PA"] = torch.empty((L, m, d), dtype=torch.int64, device=dev)
+        p["PB"] = torch.empty((L, m, d), dtype=torch.int64, device=dev)
         macs += 2 * L * m * d * d
 
     def batch(form):
@@ -199,31 +308,127 @@ def run_batch(args):
 
     # the per-product loops first, then the eager batches, then the graph-replayed batches:
     # the graphs' own workspace allocations come last, after every stream-ordered one
-    s_loop_digit = _time_steps(loop("int8"), args.steps, args.warmup)
-    s_loop_crt = _time_steps(loop("int8_crt"), args.steps, args.warmup)
+    lsteps = max(2, steps // 4)
+    s_loop_digit = _time_steps(loop("int8"), lsteps, 1) if loops else None
+    s_loop_crt = _time_steps(loop("int8_crt"), lsteps, 1) if loops else None
     hlb.set_option(hlb.OPT_BATCH_GRAPH, 0)
-    s_crt_eager = _time_steps(batch("int8_crt"), args.steps, args.warmup)
-    s_digit_eager = _time_steps(batch("int8"), args.steps, args.warmup)
+    s_crt_eager, kb = _profiled(batch("int8_crt"), ("crt_split_batch", "crt_gemm_batch", "crt_combine_batch"),
+                                steps, warmup)
+    s_digit_eager = _time_steps(batch("int8"), lsteps, 1)
     hlb.set_option(hlb.OPT_BATCH_GRAPH, 1)
-    s_crt = _time_steps(batch("int8_crt"), args.steps, args.warmup)
-    s_digit = _time_steps(batch("int8"), args.steps, args.warmup)
+    s_crt = _time_steps(batch("int8_crt"), steps, warmup)
+    s_digit = _time_steps(batch("int8"), steps, warmup)
     crt_moduli = hlb.plan(1, max(d for _, d in shapes), max(primes), 1 << 20, "int8_crt")["p_limbs"]
+    out = {
+        "value": macs / s_crt, "unit": "mod-q MAC/s", "ms_per_step": s_crt * 1e3,
+        "workload": "64 CP-MMs, d log-uniform [128, 4096], m log-uniform [64, 4096], n = d, 4 primes of "
+                    "45 bits, multimodular INT8 form, one graph-replayed batch call",
+        "moduli": crt_moduli, "mod_q_macs": macs,
+        "roofline": _roofline("crt_gemm_batch", kb["crt_gemm_batch"][0], kb["crt_gemm_batch"][1],
+                              2.0 * crt_moduli * macs, steps, "batch64", L, INT8_PEAK_TOPS, "TOP/s",
+                              "int8 MAC x 2 (useful products only)"),
+        "kernels_ms": {n: v[1] for n, v in kb.items()},
+        "eager_batch_ms": s_crt_eager * 1e3,
+        "digit_form": {"value": macs / s_digit, "ms": s_digit * 1e3, "digits": [3, 6],
+                       "eager_ms": s_digit_eager * 1e3},
+    }
+    if loops:
+        out["per_product_loop_ms"] = s_loop_crt * 1e3
+        out["batch_vs_loop_speedup"] = s_loop_crt / s_crt
+        out["digit_form"]["per_product_loop_ms"] = s_loop_digit * 1e3
+        out["digit_form"]["batch_vs_loop_speedup"] = s_loop_digit / s_digit
+    del probs
+    torch.cuda.empty_cache()
+    return out, shapes
+
+
+def run_batch(args):
+    """The batch workload alone, as its own JSON line."""
+    res, shapes = batch_leg(args.steps, args.warmup, loops=not args.no_batch_loops)
     print(json.dumps({
         "metric": "batched CP-MM mod-q MACs/s (64 uneven products, 4 RNS primes of 45 bits)",
-        "value": macs / s_crt, "unit": "mod-q MAC/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": s_crt * 1e3, "higher_is_better": True,
+        "value": res["value"], "unit": "mod-q MAC/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
-        "config": {"workload": "64 CP-MMs, d log-uniform [128, 4096], m log-uniform [64, 4096], n = d, "
-                               "4 primes of 45 bits, multimodular INT8 form, one graph-replayed batch call",
-                   "moduli": crt_moduli, "mod_q_macs": macs, "shapes_mxd": shapes},
-        "int8_tops": 2.0 * crt_moduli * macs / s_crt / 1e12,
-        "eager_batch": {"value": macs / s_crt_eager, "ms": s_crt_eager * 1e3},
-        "per_product_loop": {"value": macs / s_loop_crt, "ms": s_loop_crt * 1e3},
-        "batch_vs_loop_speedup": s_loop_crt / s_crt,
-        "digit_form": {"value": macs / s_digit, "ms": s_digit * 1e3, "digits": [3, 6],
-                       "eager_ms": s_digit_eager * 1e3, "per_product_loop_ms": s_loop_digit * 1e3,
-                       "batch_vs_loop_speedup": s_loop_digit / s_digit},
+        "config": {"workload": res["workload"], "moduli": res["moduli"], "mod_q_macs": res["mod_q_macs"],
+                   "shapes_mxd": shapes},
+        "roofline": res["roofline"],
+        **{k: v for k, v in res.items() if k not in ("value", "ms_per_step", "workload", "roofline")},
     }), flush=True)
+
+
+def _dgemm_ms(d, steps):
+    """Same-shape cleartext FP64 GEMM (vendor library through torch): d x d x d."""
+    import torch
+    dev = torch.device("cuda:0")
+    Xf = torch.rand((d, d), dtype=torch.float64, device=dev)
+    Yf = torch.rand((d, d), dtype=torch.float64, device=dev)
+    Zf = torch.empty((d, d), dtype=torch.float64, device=dev)
+    s = _time_steps(lambda: torch.matmul(Xf, Yf, out=Zf), steps, 2)
+    del Xf, Yf, Zf
+    return s * 1e3
+
+
+def config2_leg(steps, warmup):
+    """CP-MM at d = 4096 over 3 primes of 50 bits in the plain FP64-limb form (the paper's own
+    form: one plaintext limb, three 17-bit ciphertext limbs), beside the multimodular INT8
+    form on the same inputs (drawn on the device)."""
+    import torch
+
+    import paper_2503_16080_amd as hlb
+    import workloads as wl
+
+    d, L = 4096, 3
+    primes, P, A, B = wl.cpmm_uniform_device(1002, d, d, d, 50, L)
+    PA = torch.empty((L, d, d), dtype=torch.int64, device=P.device)
+    PB = torch.empty_like(PA)
+    macs = 2 * L * d ** 3
+    step = lambda form: (lambda: hlb.cp_mm(P, A, B, primes, p_absmax=1 << 20, form=form, out=(PA, PB)))
+    s_f, kf = _profiled(step("fp64"), ("gemm_f64", "prep_p", "prep_x"), steps, warmup)
+    s_c = _time_steps(step("int8_crt"), steps, warmup)
+    fplan = hlb.plan(1, d, max(primes), 1 << 20, "fp64")
+    ms_dg = _dgemm_ms(d, max(3, steps // 2))
+    out = {"value": macs / s_f, "unit": "mod-q MAC/s", "ms_per_step": s_f * 1e3,
+           "workload": f"cp_mm d={d} over {L} primes of 50 bits, FP64-limb form "
+                       f"({fplan['p_limbs']} x {fplan['x_limbs']} limbs of {fplan['limb_bits']} bits)",
+           "roofline": _roofline("gemm_f64", kf["gemm_f64"][0], kf["gemm_f64"][1],
+                                 2.0 * fplan["p_limbs"] * fplan["x_limbs"] * macs, steps, d, L,
+                                 FP64_PEAK_TFLOPS, "TFLOP/s", "fp64 MAC x 2"),
+           "kernels_ms": {n: v[1] for n, v in kf.items()},
+           "int8_multimodular_ms": s_c * 1e3, "int8_multimodular_value": macs / s_c,
+           "fp64_gemm_ms": ms_dg, "slowdown_vs_fp64_gemm": {"fp64_form": s_f * 1e3 / ms_dg,
+                                                            "int8_form": s_c * 1e3 / ms_dg}}
+    del P, A, B, PA, PB
+    torch.cuda.empty_cache()
+    return out
+
+
+def config5_leg(steps, warmup):
+    """CP-MM at d = 16384 over 2 primes of 50 bits (2 GiB per residue matrix) in the
+    multimodular INT8 form, inputs drawn on the device, against the same-shape vendor dgemm."""
+    import torch
+
+    import paper_2503_16080_amd as hlb
+    import workloads as wl
+
+    d, L = 16384, 2
+    primes, P, A, B = wl.cpmm_uniform_device(1005, d, d, d, 50, L)
+    PA = torch.empty((L, d, d), dtype=torch.int64, device=P.device)
+    PB = torch.empty_like(PA)
+    macs = 2 * L * d ** 3
+    cplan = hlb.plan(1, d, max(primes), 1 << 20, "int8_crt")
+    s_c, kc = _profiled(lambda: hlb.cp_mm(P, A, B, primes, p_absmax=1 << 20, form="int8_crt", out=(PA, PB)),
+                        ("crt_gemm", "crt_split_p", "crt_split_x", "crt_combine"), steps, warmup)
+    del P, A, B, PA, PB
+    torch.cuda.empty_cache()
+    ms_dg = _dgemm_ms(d, max(2, steps // 3))
+    return {"value": macs / s_c, "unit": "mod-q MAC/s", "ms_per_step": s_c * 1e3,
+            "workload": f"cp_mm d={d} over {L} primes of 50 bits, multimodular INT8 form "
+                        f"({cplan['p_limbs']} moduli)",
+            "roofline": _roofline("crt_gemm", kc["crt_gemm"][0], kc["crt_gemm"][1], 2.0 * cplan["p_limbs"] * macs,
+                                  steps, d, L, INT8_PEAK_TOPS, "TOP/s", "int8 MAC x 2"),
+            "kernels_ms": {n: v[1] for n, v in kc.items()},
+            "fp64_gemm_ms": ms_dg, "slowdown_vs_fp64_gemm": s_c * 1e3 / ms_dg}
 
 
 def run_trunc(args):
@@ -333,8 +538,18 @@ def trunc_precision(d, q, budget_fp64, budgets_int8):
 def main():
     args = _parse()
     if args.summarize_counters:
+        tag = "batch64" if args.workload == "batch" else args.d
+        L = 4 if args.workload == "batch" else args.primes
         for kernel in TRAFFIC:
-            print(json.dumps(summarize_counters(*args.summarize_counters, args.d, args.primes, kernel)))
+            out = summarize_counters(*args.summarize_counters, tag, L, kernel)
+            if out is not None:
+                print(json.dumps(out))
+        return
+    if args.summarize_mfma:
+        for kernel in TRAFFIC:
+            out = summarize_mfma(args.summarize_mfma, args.d, args.primes, kernel)
+            if out is not None:
+                print(json.dumps(out))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the CP-MM path has no multi-GPU leg); "
@@ -377,29 +592,10 @@ def main():
 
     def timed(form, names, steps, warmup):
         """Step time of `form` with its kernels bracketed by HIP events on the launch stream."""
-        for _ in range(warmup):
-            step(form)()
-        torch.cuda.synchronize()
-        hlb.profile_reset()
-        hlb.set_option(hlb.OPT_PROFILE, 1)
-        s = _time_steps(step(form), steps, 0)
-        hlb.set_option(hlb.OPT_PROFILE, 0)
-        prof = {n: hlb.profile_read(n) for n in names}
-        hlb.profile_reset()
-        return s, {n: (c, t / max(c, 1)) for n, (c, t) in prof.items()}
+        return _profiled(step(form), names, steps, warmup)
 
     def roofline(kernel, launches, ms, ops_per_step, steps):
-        # a step may cut the GEMM into several launches (one per right operand): the
-        # algorithmic work of one launch is the step's work over its launches
-        per_step = launches / steps
-        ops = ops_per_step / per_step
-        tops = ops / (ms * 1e-3) / 1e12
-        traffic = measured_traffic(kernel, d, L)
-        return {"bound": "mfma", "achieved": tops, "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
-                "frac": tops / INT8_PEAK_TOPS, "traffic": traffic,
-                "traffic_gbs": None if traffic is None else traffic / (ms * 1e-3) / 1e9,
-                "kernel": TRAFFIC[kernel]["match"], "avg_launch_ms": ms, "launches": launches,
-                "launches_per_step": per_step, "ops_per_launch": ops, "op": "int8 MAC x 2"}
+        return _roofline(kernel, launches, ms, ops_per_step, steps, d, L, INT8_PEAK_TOPS, "TOP/s", "int8 MAC x 2")
 
     # Headline: the multimodular INT8 form (Strategy 3; D int8 products per mod-q MAC)
     cplan = hlb.plan(1, d, max(w.primes), w.p_absmax, "int8_crt")
@@ -447,12 +643,7 @@ def main():
         fplan = hlb.plan(1, d, max(w.primes), w.p_absmax, "fp64")
         f_ops = 2.0 * fplan["p_limbs"] * fplan["x_limbs"] * macs
         f_tf = f_ops / (ms_f / max(n_f, 1) * 1e-3) / 1e12
-        # same-shape cleartext FP64 GEMM (vendor library through torch): d x d x d
-        Xf = torch.rand((d, d), dtype=torch.float64, device=dev)
-        Yf = torch.rand((d, d), dtype=torch.float64, device=dev)
-        Zf = torch.empty((d, d), dtype=torch.float64, device=dev)
-        s_dgemm = _time_steps(lambda: torch.matmul(Xf, Yf, out=Zf), max(3, args.steps // 2), 2)
-        del Xf, Yf, Zf
+        s_dgemm = _dgemm_ms(d, max(3, args.steps // 2)) * 1e-3
         out["fp64_form"] = {"value": macs / s_fp64, "unit": "mod-q MAC/s", "ms_per_step": s_fp64 * 1e3,
                             "limbs": [fplan["p_limbs"], fplan["x_limbs"]], "limb_bits": fplan["limb_bits"],
                             "gemm_tflops": f_tf, "gemm_frac_of_fp64_peak": f_tf / FP64_PEAK_TFLOPS}
@@ -462,6 +653,13 @@ def main():
         out["slowdown_vs_fp64_gemm"] = {"int8_form": s_crt / s_dgemm, "fp64_form": s_fp64 / s_dgemm}
         if "int8_digit_form" in out:
             out["slowdown_vs_fp64_gemm"]["int8_digit_form"] = s_dig / s_dgemm
+
+    if not args.no_extra_configs:
+        del P, A, B, PA, PB
+        torch.cuda.empty_cache()
+        out["config2_d4096_fp64"] = config2_leg(max(3, args.steps // 2), 2)
+        out["config5_d16384_int8"] = config5_leg(max(3, args.steps // 4), 1)
+        out["config4_batch64"], _ = batch_leg(args.steps, args.warmup)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)

@@ -36,7 +36,8 @@ OPT_WS_CAP = 7
 NOALLOC_SCRATCH_BYTES = 256 << 20   # HLB_NOALLOC_SCRATCH_BYTES
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libhlb.so")
+# HLB_LIBRARY selects another build of the same library (the host-sanitizer build)
+_LIB_PATH = os.environ.get("HLB_LIBRARY") or os.path.join(_HERE, "libhlb.so")
 _lib = None
 _lock = threading.Lock()
 
