@@ -26,6 +26,7 @@ import json
 import os
 import sys
 import time
+import types
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -579,16 +580,21 @@ def main():
 
     d, L = args.d, args.primes
     seed = 1003
-    w = wl.cpmm_uniform(seed, d, d, d, args.bits, L)
-    dev = torch.device("cuda:0")
-    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev)
-    P, A, B = t(w.P), t(w.A), t(w.B)
+    # inputs drawn on the device (the distributions of workloads.cpmm_uniform); the CPU baseline
+    # reads host copies of the same tensors
+    primes, P, A, B = wl.cpmm_uniform_device(seed, d, d, d, args.bits, L)
+    p_absmax = 1 << 20
+    dev = P.device
+    w = None
+    if not args.no_cpu_baseline:
+        w = types.SimpleNamespace(m=d, k=d, nA=d, nB=d, primes=primes, P=P.cpu().numpy(),
+                                  A=A.cpu().numpy().view(np.uint64), B=B.cpu().numpy().view(np.uint64))
     PA = torch.empty((L, d, d), dtype=torch.int64, device=dev)
     PB = torch.empty((L, d, d), dtype=torch.int64, device=dev)
     macs = 2 * L * d * d * d  # mod-q MACs per step
 
     def step(form):
-        return lambda: hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form=form, out=(PA, PB))
+        return lambda: hlb.cp_mm(P, A, B, primes, p_absmax=p_absmax, form=form, out=(PA, PB))
 
     def timed(form, names, steps, warmup):
         """Step time of `form` with its kernels bracketed by HIP events on the launch stream."""
@@ -598,7 +604,7 @@ def main():
         return _roofline(kernel, launches, ms, ops_per_step, steps, d, L, INT8_PEAK_TOPS, "TOP/s", "int8 MAC x 2")
 
     # Headline: the multimodular INT8 form (Strategy 3; D int8 products per mod-q MAC)
-    cplan = hlb.plan(1, d, max(w.primes), w.p_absmax, "int8_crt")
+    cplan = hlb.plan(1, d, max(primes), p_absmax, "int8_crt")
     s_crt, kc = timed("int8_crt", ("crt_gemm", "crt_split_p", "crt_split_x", "crt_combine"), args.steps,
                       args.warmup)
     c_ops = 2.0 * cplan["p_limbs"] * macs
@@ -621,7 +627,7 @@ def main():
 
     # The digit INT8 form (Strategy 1: 3 x 7 digit products per mod-q MAC)
     if not args.no_digit:
-        dplan = hlb.plan(1, d, max(w.primes), w.p_absmax, "int8")
+        dplan = hlb.plan(1, d, max(primes), p_absmax, "int8")
         s_dig, kd = timed("int8", ("gemm_i8", "split_p", "split_x"), args.steps, args.warmup)
         d_ops = 2.0 * dplan["p_limbs"] * dplan["x_limbs"] * macs
         out["int8_digit_form"] = {
@@ -640,7 +646,7 @@ def main():
         hlb.set_option(hlb.OPT_PROFILE, 0)
         n_f, ms_f = hlb.profile_read("gemm_f64")
         hlb.profile_reset()
-        fplan = hlb.plan(1, d, max(w.primes), w.p_absmax, "fp64")
+        fplan = hlb.plan(1, d, max(primes), p_absmax, "fp64")
         f_ops = 2.0 * fplan["p_limbs"] * fplan["x_limbs"] * macs
         f_tf = f_ops / (ms_f / max(n_f, 1) * 1e-3) / 1e12
         s_dgemm = _dgemm_ms(d, max(3, args.steps // 2)) * 1e-3

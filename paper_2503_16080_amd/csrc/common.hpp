@@ -108,6 +108,29 @@ __device__ __forceinline__ void copy_to_lds(const int8_t *src, int8_t *dst, int 
     }
 }
 
+// The same copy with the buffer form of the direct-to-LDS load (MUBUF ... lds): the source
+// is `rsrc` + src_off, byte offsets below 2^32.  The compiler counts these loads in vmcnt only,
+// so LDS fragment reads after them can wait for just the reads they need.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t lds_src_rsrc(const int8_t *base) {
+    // the base is wave-uniform; say so, so that the descriptor lives in scalar registers
+    const uint64_t p = (uint64_t)(uintptr_t)base;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(uintptr_t)(((uint64_t)hi << 32) | lo), 0, 0xffffffff,
+                                             0x00020000);
+}
+template <int THREADS, int CHUNKS>
+__device__ __forceinline__ void copy_to_lds_buf(__amdgpu_buffer_rsrc_t rsrc, uint32_t src_off, int8_t *dst, int tid,
+                                                int wave_u) {
+#pragma unroll
+    for (int i = 0; i < (CHUNKS + THREADS - 1) / THREADS; ++i) {
+        const int base = i * THREADS + wave_u * 64;  // wave-uniform
+        if (CHUNKS % THREADS == 0 || base < CHUNKS)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)(dst + base * 16),
+                                                     16, src_off + (uint32_t)(i * THREADS + tid) * 16u, 0, 0, 0);
+    }
+}
+
 // Direct-to-LDS loads a wave issues for one stage (chunks are dealt in runs of 64).
 template <int THREADS, int CHUNKS>
 __device__ __forceinline__ int loads_of_wave(int wave_u) {

@@ -234,14 +234,18 @@ __device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const in
         for (int b = 0; b < NB; ++b) acc[a][b] = v16i{0};
 
     constexpr int CH = kCrtSub / 16;  // 16-byte chunks per block
+    // the buffer form of the direct-to-LDS load (byte offsets within a tile's panels stay
+    // below 2^32: at most 3 x 2048 k blocks x 16 moduli x 8 KiB)
+    const __amdgpu_buffer_rsrc_t rsP = lds_src_rsrc(gP), rsX = lds_src_rsrc(gX);
     auto gload = [&](int kb, int buf) {
         int8_t *dst = lds + buf * T::STAGE;
-        const int64_t off = (int64_t)kb * plane_stride;
+        const uint32_t off = (uint32_t)kb * (uint32_t)plane_stride;
 #pragma unroll
-        for (int b = 0; b < 2; ++b) copy_to_lds<kCrtThreads, CH>(gP + b * tile_stride + off, dst + b * kCrtSub, tid, wave_u);
+        for (int b = 0; b < 2; ++b)
+            copy_to_lds_buf<kCrtThreads, CH>(rsP, (uint32_t)(b * tile_stride) + off, dst + b * kCrtSub, tid, wave_u);
 #pragma unroll
         for (int b = 0; b < T::XSUB; ++b)
-            copy_to_lds<kCrtThreads, CH>(gX + b * tile_stride + off, dst + (2 + b) * kCrtSub, tid, wave_u);
+            copy_to_lds_buf<kCrtThreads, CH>(rsX, (uint32_t)(b * tile_stride) + off, dst + (2 + b) * kCrtSub, tid, wave_u);
     };
     const int loads_per_stage = (2 + T::XSUB) * loads_of_wave<kCrtThreads, CH>(wave_u);
 
@@ -252,21 +256,25 @@ __device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const in
     struct Frags {
         v4i a[MB], b[NB];
     };
-    auto read_frags = [&](Frags &f, int buf, int kk) {
+    // the fragments of row block mb / column block nb for K half kk of the stage in buffer buf
+    auto frag_a = [&](int buf, int kk, int mb) -> v4i {
         const int8_t *lp = lds + buf * T::STAGE + psub * kCrtSub;
+        const int c = kk * 2 + (lane >> 5);
+        const int r = prow0 + mb * 32 + (lane & 31);
+        return *(const v4i *)(lp + r * 64 + ((c ^ swz(r)) << 4));
+    };
+    auto frag_b = [&](int buf, int kk, int nb) -> v4i {
         const int8_t *lx = lds + buf * T::STAGE + 2 * kCrtSub;
         const int c = kk * 2 + (lane >> 5);
+        const int col = wn * 32 * NB + nb * 32 + (lane & 31);
+        const int r = col & (kCrtR - 1);
+        return *(const v4i *)(lx + (col / kCrtR) * kCrtSub + r * 64 + ((c ^ swz(r)) << 4));
+    };
+    auto read_frags = [&](Frags &f, int buf, int kk) {
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            const int r = prow0 + mb * 32 + (lane & 31);
-            f.a[mb] = *(const v4i *)(lp + r * 64 + ((c ^ swz(r)) << 4));
-        }
+        for (int mb = 0; mb < MB; ++mb) f.a[mb] = frag_a(buf, kk, mb);
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int col = wn * 32 * NB + nb * 32 + (lane & 31);
-            const int r = col & (kCrtR - 1);
-            f.b[nb] = *(const v4i *)(lx + (col / kCrtR) * kCrtSub + r * 64 + ((c ^ swz(r)) << 4));
-        }
+        for (int nb = 0; nb < NB; ++nb) f.b[nb] = frag_b(buf, kk, nb);
     };
     auto mfmas = [&](const Frags &f) {
 #pragma unroll
@@ -292,29 +300,72 @@ __device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const in
     wait_vmcnt(outstanding(G - 1, kCrtNbuf - 1));
     stage_barrier();
     if constexpr (MB * NB >= 12) {
-        // 192 accumulator registers leave room for one half-stage of fragments: each half
-        // reads its own, and the other wave on the SIMD covers the wait
+        // One half-stage of fragments in registers, refilled in place: the MFMAs of a half run
+        // column block by column block (nb outer), so b[nb] is dead after its MB MFMAs and each
+        // a[mb] after its use in the last column block; each register set is refilled with the
+        // next half's fragment as soon as it dies, and the next half starts with the fragments
+        // refilled first.  Only the first half after each workgroup barrier waits for all of
+        // its reads.  Full groups of G stages run branch-free; a last partial group takes the
+        // plain schedule.
+        static_assert(G == 2, "four halves per group");
+        // the MFMAs of one half from f; with NEXT, refill f from (nbuf, nkk) as registers die
+        auto half = [&](Frags &f, bool next, int nbuf, int nkk) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    acc[mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a[mb], f.b[nb], acc[mb][nb], 0, 0, 0);
+                    if (next) {
+                        if (nb < NB - 1 && mb == MB - 1) f.b[nb] = frag_b(nbuf, nkk, nb);
+                        if (nb == NB - 1) {
+                            f.a[mb] = frag_a(nbuf, nkk, mb);
+                            if (mb == MB - 1) f.b[nb] = frag_b(nbuf, nkk, nb);
+                        }
+                    }
+                }
+            }
+            if (next) {
+                // pin the order: MB MFMAs then one read per column block but the last, then
+                // one read after each MFMA of the last column block (two after the final one)
+#pragma unroll
+                for (int nb = 0; nb < NB - 1; ++nb) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, MB, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                }
+#pragma unroll
+                for (int mb = 0; mb < MB - 1; ++mb) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        const int KBfull = KB - KB % G;
+        Frags f;
 #pragma unroll 1
-        for (int kb = 0; kb < KB; kb += G) {
+        for (int kb = 0; kb < KBfull; kb += G) {
+            const int b0 = kb % kCrtNbuf, b1 = (kb + 1) % kCrtNbuf;
+            read_frags(f, b0, 0);
+            half(f, true, b0, 1);
+            half(f, true, b1, 0);
+            half(f, true, b1, 1);
+            half(f, false, 0, 0);
+            wait_lds_after_mfmas();
+            wait_vmcnt(outstanding(kb + 2 * G - 1, kb + kCrtNbuf - 1));
+            stage_barrier();
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int st = kb + g;
-                if (st >= KB) break;
-                const int cur = st % kCrtNbuf;
+            for (int h = 0; h < G; ++h)
+                if (kb + h + kCrtNbuf < KB) gload(kb + h + kCrtNbuf, (kb + h) % kCrtNbuf);
+        }
+        if (KBfull < KB) {
+            const int cur = KBfull % kCrtNbuf;
 #pragma unroll
-                for (int kk = 0; kk < 2; ++kk) {
-                    Frags f;
-                    read_frags(f, cur, kk);
-                    mfmas(f);
-                }
-                if (g == G - 1 || st + 1 == KB) {
-                    wait_lds_after_mfmas();
-                    wait_vmcnt(outstanding(kb + 2 * G - 1, kb + kCrtNbuf - 1));
-                    stage_barrier();
-#pragma unroll
-                    for (int h = 0; h < G; ++h)
-                        if (kb + h + kCrtNbuf < KB) gload(kb + h + kCrtNbuf, (kb + h) % kCrtNbuf);
-                }
+            for (int kk = 0; kk < 2; ++kk) {
+                read_frags(f, cur, kk);
+                mfmas(f);
             }
         }
     } else {
