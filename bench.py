@@ -78,13 +78,14 @@ _CSRC = os.path.join(ROOT, "paper_2503_16080_amd", "csrc")
 # Counter summaries per GEMM kernel: the sources whose SHA-256 they are valid for, and the
 # kernel-name substring that selects their dispatches.  One file per kernel and workload.
 TRAFFIC = {
-    "crt_gemm": {"sources": [os.path.join(_CSRC, f) for f in ("crt.hip", "crt.hpp", "common.hpp")],
+    "crt_gemm": {"sources": [os.path.join(_CSRC, f) for f in ("crt_gemm.hip", "crt.hpp", "common.hpp")],
                  "match": "crt_gemm_kernel"},
     "gemm_i8": {"sources": [os.path.join(_CSRC, f) for f in ("gemm_i8.hip", "i8_tile.hpp", "common.hpp")],
                 "match": "gemm_i8_kernel"},
     "gemm_f64": {"sources": [os.path.join(_CSRC, f) for f in ("gemm_f64_planes.hip", "common.hpp")],
                  "match": "gemm_f64_planes_kernel"},
-    "crt_gemm_batch": {"sources": [os.path.join(_CSRC, f) for f in ("crt.hip", "crt.hpp", "common.hpp", "batch.hip")],
+    "crt_gemm_batch": {"sources": [os.path.join(_CSRC, f)
+                                   for f in ("crt_gemm.hip", "crt.hpp", "common.hpp", "batch.hip")],
                        "match": "crt_gemm_batch_kernel"},
 }
 
@@ -419,7 +420,7 @@ def config5_leg(steps, warmup):
     macs = 2 * L * d ** 3
     cplan = hlb.plan(1, d, max(primes), 1 << 20, "int8_crt")
     s_c, kc = _profiled(lambda: hlb.cp_mm(P, A, B, primes, p_absmax=1 << 20, form="int8_crt", out=(PA, PB)),
-                        ("crt_gemm", "crt_split_p", "crt_split_x", "crt_combine"), steps, warmup)
+                        ("crt_gemm", "crt_split", "crt_combine"), steps, warmup)
     del P, A, B, PA, PB
     torch.cuda.empty_cache()
     ms_dg = _dgemm_ms(d, max(2, steps // 3))
@@ -605,7 +606,7 @@ def main():
 
     # Headline: the multimodular INT8 form (Strategy 3; D int8 products per mod-q MAC)
     cplan = hlb.plan(1, d, max(primes), p_absmax, "int8_crt")
-    s_crt, kc = timed("int8_crt", ("crt_gemm", "crt_split_p", "crt_split_x", "crt_combine"), args.steps,
+    s_crt, kc = timed("int8_crt", ("crt_gemm", "crt_split", "crt_combine"), args.steps,
                       args.warmup)
     c_ops = 2.0 * cplan["p_limbs"] * macs
     out = {

@@ -305,10 +305,14 @@ int hlb_tune_class(int x_digits, int64_t m, int64_t n, int64_t k);
 
 /*
  * Kernel timing collected while HLB_OPT_PROFILE is on (synchronous: waits for the
- * recorded events).  For kernel class `name` ("gemm_i8", "gemm_f64", "split_p",
- * "split_x", "batch_i8"), *launches receives the number of launches and *total_ms their
- * summed durations measured between events recorded on each launch's stream.  Unknown
- * names report zero.  Collected records are cleared by hlb_profile_reset().
+ * recorded events).  For kernel class `name`, *launches receives the number of launches and
+ * *total_ms their summed durations measured between events recorded on each launch's stream.
+ * Classes: multimodular form "crt_split" (residue splits of one call), "crt_gemm",
+ * "crt_combine" (recombinations); its batch "crt_split_batch", "crt_gemm_batch",
+ * "crt_combine_batch"; digit form "split_p", "split_x", "gemm_i8", "gemm_i8_trunc", its
+ * batch "batch_i8"; FP64 form "prep_p", "prep_x", "gemm_f64", "gemm_f64_trunc".  Launches
+ * inside a graph capture are not recorded.  Unknown names report zero.  Collected records
+ * are cleared by hlb_profile_reset().
  */
 hlb_status hlb_profile_read(const char *name, int64_t *launches, double *total_ms);
 hlb_status hlb_profile_reset(void);

@@ -19,6 +19,7 @@
 #include "launch.hpp"
 #include "host.hpp"
 #include "crt.hpp"
+#include "crt_jobs.hpp"
 
 namespace hlb {
 
@@ -420,13 +421,43 @@ void ws_free(void *p, hipStream_t s) {
 
 // Per-stream blocks.  A pool allocation per call was measured to degrade: after a few hundred
 // calls alternating shapes and forms, hipMallocAsync averaged 1.3 ms and reached seconds.
+// Each slot records an event on its stream when a call's lease ends; the next call that takes
+// the block waits for it on its own stream first.  Calls on one stream are ordered anyway, but
+// a destroyed stream's handle may be handed to a new stream, whose work would otherwise not
+// be ordered after the old stream's use of the block.  A device keeps at most kMaxSlotBlocks
+// blocks: taking one beyond that frees the least recently used idle block (after its event).
 struct WsSlot {
     std::mutex mu;  // held by the lease of the call using the block
     void *p = nullptr;
     size_t bytes = 0;
+    hipEvent_t done = nullptr;  // recorded on the stream at the end of each lease
+    uint64_t last_use = 0;
+    int dev = 0;
 };
 static std::mutex g_slots_mu;
 static std::map<std::pair<int, hipStream_t>, WsSlot *> g_slots;
+static uint64_t g_slot_tick = 0;  // guarded by g_slots_mu
+constexpr int kMaxSlotBlocks = 4;
+
+// Frees idle blocks of device `dev` (least recently used first) until at most keep - 1 other
+// blocks remain besides `self`; a block still in use by another thread is skipped.
+static void ws_evict_lru(int dev, const WsSlot *self, hipStream_t s, int keep) {
+    std::lock_guard<std::mutex> g(g_slots_mu);
+    std::vector<WsSlot *> held;
+    for (auto &kv : g_slots)
+        if (kv.second != self && kv.second->dev == dev && kv.second->p) held.push_back(kv.second);
+    if ((int)held.size() < keep) return;
+    std::sort(held.begin(), held.end(), [](const WsSlot *a, const WsSlot *b) { return a->last_use < b->last_use; });
+    for (size_t i = 0; i + (size_t)keep <= held.size(); ++i) {
+        WsSlot *v = held[i];
+        if (!v->mu.try_lock()) continue;
+        if (v->done) (void)hipEventSynchronize(v->done);
+        if (v->p) (void)hipFreeAsync(v->p, s);
+        v->p = nullptr;
+        v->bytes = 0;
+        v->mu.unlock();
+    }
+}
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
@@ -469,10 +500,20 @@ hlb_status WsLease::take(hipStream_t s, const size_t *bytes, void **ptrs, int n)
         {
             std::lock_guard<std::mutex> g(g_slots_mu);
             WsSlot *&sl = g_slots[{dev, s}];
-            if (!sl) sl = new WsSlot;
+            if (!sl) {
+                sl = new WsSlot;
+                sl->dev = dev;
+            }
             slot_ = sl;
+            slot_->last_use = ++g_slot_tick;
         }
         slot_->mu.lock();
+        // work enqueued on this stream handle before (possibly by a stream since destroyed)
+        if (slot_->done && hipStreamWaitEvent(s, slot_->done, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            return HLB_EDEVICE;  // the destructor unlocks
+        }
+        if (!slot_->p) ws_evict_lru(dev, slot_, s, kMaxSlotBlocks);
         if (slot_->bytes < total) {
             // the old block's last users precede this call in stream order
             if (slot_->p) (void)hipFreeAsync(slot_->p, s);
@@ -498,7 +539,14 @@ hlb_status WsLease::take(hipStream_t s, const size_t *bytes, void **ptrs, int n)
 
 WsLease::~WsLease() {
     if (own_) (void)hipFreeAsync(own_, s_);
-    if (slot_) slot_->mu.unlock();
+    if (slot_) {
+        if (!slot_->done && hipEventCreateWithFlags(&slot_->done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            slot_->done = nullptr;
+        }
+        if (slot_->done && hipEventRecord(slot_->done, s_) != hipSuccess) (void)hipGetLastError();
+        slot_->mu.unlock();
+    }
 }
 
 // Frees every stream's block (the device work that used them must have completed).
@@ -582,18 +630,61 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
             y0 += (int64_t)D * (t128_m / 2 * 256) * (t128_n[i] * 128);
         }
     }
-    auto split_x = [&](size_t i, hipStream_t st) -> bool {
-        ProfScope ps("crt_split_x", st);
-        return launch_crt_split_cols(D, rights[i].X, rights[i].ldx, k, rights[i].n, (int)t128_n[i], (int)kblocks,
-                                     rights[i].q, (int8_t *)wsX + x_tile0[i] * kblocks * sub, st) == hipSuccess;
-    };
     // a left operand holding residues is centred modulo the (shared) modulus of the products
     const uint64_t left_qc = pl.kind == 0 ? rights[0].q : 0;
+    // Splits go out in launches of up to kCrtTabSplit operands (the job table travels in the
+    // kernel arguments): every right operand, and the left operand too when there is only one.
+    CrtSplitTable stab;
+    int64_t swgs = 0;
+    auto split_reset = [&]() {
+        std::memset(&stab, 0, sizeof(stab));
+        for (int i = 0; i < kCrtTabSplit; ++i) stab.start[i] = INT32_MAX;
+        swgs = 0;
+    };
+    split_reset();
+    auto split_flush = [&](hipStream_t st) -> bool {
+        if (stab.njobs == 0) return true;
+        ProfScope ps("crt_split", st);
+        const bool ok = launch_crt_split_tab(D, stab, swgs, inv, st) == hipSuccess;
+        split_reset();
+        return ok;
+    };
+    auto split_add = [&](const CrtSplitJob &j, int64_t wgs, hipStream_t st) -> bool {
+        if ((stab.njobs == kCrtTabSplit || swgs + wgs > INT32_MAX / 2) && !split_flush(st)) return false;
+        if (wgs > INT32_MAX / 2) return false;
+        stab.start[stab.njobs] = (int32_t)swgs;
+        CrtSplitJob &e = stab.job[stab.njobs++];
+        e = j;
+        e.wg_start = swgs;
+        swgs += wgs;
+        return true;
+    };
+    auto split_x = [&](size_t i, hipStream_t st) -> bool {
+        CrtSplitJob j;
+        std::memset(&j, 0, sizeof(j));
+        j.src = rights[i].X;
+        j.ld = rights[i].ldx;
+        j.extent = rights[i].n;
+        j.k = k;
+        j.qc = rights[i].q;
+        j.kblocks = (int32_t)kblocks;
+        j.rows_side = 0;
+        j.out = (int8_t *)wsX + x_tile0[i] * kblocks * sub;
+        return split_add(j, t128_n[i] * kblocks, st);
+    };
     auto split_p = [&](const LeftSpec &L, hipStream_t st) -> bool {
-        ProfScope ps("crt_split_p", st);
         const int64_t lt = ((L.m + 255) / 256) * 2;
-        return launch_crt_split_rows(D, L.P, L.ldp, L.m, k, (int)lt, (int)kblocks, left_qc, inv, (int8_t *)wsP, st) ==
-               hipSuccess;
+        CrtSplitJob j;
+        std::memset(&j, 0, sizeof(j));
+        j.src = L.P;
+        j.ld = L.ldp;
+        j.extent = L.m;
+        j.k = k;
+        j.qc = left_qc;
+        j.kblocks = (int32_t)kblocks;
+        j.rows_side = 1;
+        j.out = (int8_t *)wsP;
+        return split_add(j, lt * kblocks, st);
     };
     // product planes of right operand i for left operand L
     auto segment = [&](const LeftSpec &L, size_t i) {
@@ -633,11 +724,34 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
         ProfScope ps("crt_gemm", st);
         return launch_crt_gemm(wide, a, st) == hipSuccess;
     };
+    // Recombinations go out in launches of up to kCrtTabCombine output matrices.
+    CrtCombineTable ctab;
+    int64_t cwgs = 0;
+    auto combine_reset = [&]() {
+        std::memset(&ctab, 0, sizeof(ctab));
+        for (int i = 0; i < kCrtTabCombine; ++i) ctab.start[i] = INT32_MAX;
+        cwgs = 0;
+    };
+    combine_reset();
+    auto combine_flush = [&](hipStream_t st) -> bool {
+        if (ctab.njobs == 0) return true;
+        ProfScope ps("crt_combine", st);
+        const bool ok = launch_crt_combine_tab(ctab, cwgs, st) == hipSuccess;
+        combine_reset();
+        return ok;
+    };
     auto combine = [&](const LeftSpec &L, size_t i, hipStream_t st) -> bool {
         if (rights[i].n == 0) return true;
         const CrtSeg sg = segment(L, i);
-        CrtCombineArgs c;
-        std::memset(&c, 0, sizeof(c));
+        const int64_t wgs = crt_combine_wgs(L.m, sg.n);
+        if ((ctab.njobs == kCrtTabCombine || cwgs + wgs > INT32_MAX / 2) && !combine_flush(st)) return false;
+        if (wgs > INT32_MAX / 2) return false;
+        ctab.start[ctab.njobs] = (int32_t)cwgs;
+        CrtCombineJob &j = ctab.job[ctab.njobs++];
+        std::memset(&j, 0, sizeof(j));
+        j.wg_start = cwgs;
+        cwgs += wgs;
+        CrtCombineArgs &c = j.a;
         c.Y = sg.Y;
         c.C = L.C[i];
         c.m = L.m;
@@ -649,32 +763,29 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
         c.barrett = (uint64_t)((~(unsigned __int128)0 >> 64) / c.q);
         c.Mq = (uint64_t)(M % c.q);
         c.D = D;
-        for (int j = 0; j < D; ++j) {
-            c.w[j] = (uint64_t)((M / (unsigned)kCrtModuli[j]) % c.q);
-            c.pinv[j] = 1.0f / (float)kCrtModuli[j];
+        for (int jj = 0; jj < D; ++jj) {
+            c.w[jj] = (uint64_t)((M / (unsigned)kCrtModuli[jj]) % c.q);
+            c.pinv[jj] = 1.0f / (float)kCrtModuli[jj];
         }
-        ProfScope ps("crt_combine", st);
-        return launch_crt_combine(c, st) == hipSuccess;
+        return true;
     };
 
+    // one left operand: its split joins the right operands' (the planes of P are shared by
+    // every GEMM launch); several: each is split before its own GEMMs, into the same planes
+    const bool one_left = lefts.size() == 1;
+    if (one_left && lefts[0].m > 0 && !split_p(lefts[0], s)) return HLB_EDEVICE;
     for (size_t i = 0; i < rights.size(); ++i)
-        if (!split_x(i, s)) {
-            return HLB_EDEVICE;
-        }
+        if (!split_x(i, s)) return HLB_EDEVICE;
+    if (!split_flush(s)) return HLB_EDEVICE;
     for (const LeftSpec &L : lefts) {
         if (L.m == 0) continue;
-        if (!split_p(L, s)) {
-            return HLB_EDEVICE;
-        }
+        if (!one_left && (!split_p(L, s) || !split_flush(s))) return HLB_EDEVICE;
         for (size_t first = 0; first < rights.size(); first += kMaxSegs) {
             const size_t last = std::min(rights.size(), first + kMaxSegs);
-            if (!gemm(L, first, last, s)) {
-                return HLB_EDEVICE;
-            }
+            if (!gemm(L, first, last, s)) return HLB_EDEVICE;
             for (size_t i = first; i < last; ++i)
-                if (!combine(L, i, s)) {
-                    return HLB_EDEVICE;
-                }
+                if (!combine(L, i, s)) return HLB_EDEVICE;
+            if (!combine_flush(s)) return HLB_EDEVICE;
         }
     }
     return HLB_OK;

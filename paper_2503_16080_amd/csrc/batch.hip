@@ -27,6 +27,7 @@
 #include "host.hpp"
 #include "launch.hpp"
 #include "crt.hpp"
+#include "crt_jobs.hpp"
 
 namespace hlb {
 

@@ -54,17 +54,12 @@ hipError_t launch_gemm_f64_planes(int nx, bool trunc, const GemmArgs &a, hipStre
 bool crt_supported_d(int D);
 int crt_round_d(int D);  // smallest supported D >= D, or 0
 struct CrtScale;
-hipError_t launch_crt_split_rows(int D, const int64_t *P, int64_t ldp, int64_t m, int64_t k, int tiles, int kblocks,
-                                 uint64_t qc, const CrtScale &scale, int8_t *out, hipStream_t s);
-hipError_t launch_crt_split_cols(int D, const uint64_t *X, int64_t ldx, int64_t k, int64_t n, int tiles, int kblocks,
-                                 uint64_t qc, int8_t *out, hipStream_t s);
 struct CrtGemmArgs;
 struct CrtCombineArgs;
 // variant 0: 256 x 128 output tiles; 1: 256 x 256 (both 8 waves).  crt_tile_cols gives the
 // tile width.
 int crt_tile_cols(int variant);
 hipError_t launch_crt_gemm(int variant, const CrtGemmArgs &a, hipStream_t s);
-hipError_t launch_crt_combine(const CrtCombineArgs &a, hipStream_t s);
 // Batched forms: one launch for many operands (jobs in increasing wg_start), one GEMM launch
 // for many problems (256 x crt_batch_tile_cols() tiles), one launch for many recombinations
 // (crt_combine_wgs workgroups each).
@@ -77,6 +72,13 @@ int crt_batch_tile_cols();
 hipError_t launch_crt_gemm_batch(const CrtBatchArgs &a, hipStream_t s);
 int64_t crt_combine_wgs(int64_t m, int64_t n);
 hipError_t launch_crt_combine_batch(const CrtCombineJob *jobs, int njobs, int64_t total_wgs, hipStream_t s);
+// The same two with the job tables in the kernel arguments (at most kCrtTabSplit operands /
+// kCrtTabCombine outputs per launch).
+struct CrtSplitTable;
+struct CrtCombineTable;
+hipError_t launch_crt_split_tab(int D, const CrtSplitTable &t, int64_t total_wgs, const CrtScale &scale,
+                                hipStream_t s);
+hipError_t launch_crt_combine_tab(const CrtCombineTable &t, int64_t total_wgs, hipStream_t s);
 
 // Auxiliary kernels.
 hipError_t launch_validate(const uint64_t *X, int64_t rows, int64_t cols, int64_t ld, uint64_t q,

@@ -133,3 +133,23 @@ def test_capture_with_measured_bound_is_refused_before_any_enqueue():
     # the same call outside capture measures the bound and is exact
     PA2, PB2 = hlb.cp_mm(P, A, B, w.primes, p_absmax=0, form="int8_crt")
     assert np.array_equal(_np(PA2), want[0]) and np.array_equal(_np(PB2), want[1])
+
+
+def test_many_short_lived_streams_reuse_and_evict_blocks():
+    # torch hands out pooled stream handles round-robin, so the calls below reuse handles of
+    # streams whose Python objects are gone, and touch more streams than the library keeps
+    # workspace blocks for (older blocks are freed after their last use): nothing is
+    # synchronised on the host until the end, and every result must match the oracle.
+    cases = [_case(90 + i, s) for i, s in enumerate(SHAPES)]
+    torch.cuda.synchronize()
+    pending = []
+    for rep in range(3):
+        for i, (w, want) in enumerate(cases):
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                P, A, B = _t(w.P), _t(w.A), _t(w.B)
+                out = hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form=FORMS[(i + rep) % 3], stream=st)
+            pending.append((rep, i, want, out))
+    torch.cuda.synchronize()
+    for rep, i, want, (PA, PB) in pending:
+        assert np.array_equal(_np(PA), want[0]) and np.array_equal(_np(PB), want[1]), (rep, i)
