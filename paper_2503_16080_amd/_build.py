@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhlb.so")
 
-SOURCES = ["gemm_i8.hip", "gemm_i8_trunc.hip", "gemm_f64.hip", "gemm_f64_planes.hip", "crt.hip", "crt_gemm.hip", "aux.hip", "batch.hip", "noalloc.hip", "api.cpp"]
+SOURCES = ["gemm_i8.hip", "gemm_i8_trunc.hip", "gemm_f64.hip", "gemm_f64_planes.hip", "crt.hip", "crt_gemm.hip", "crt_gemm_batch.hip", "aux.hip", "batch.hip", "noalloc.hip", "api.cpp"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -271,7 +271,7 @@ struct CrtBatchLayout {
     int64_t total_items = 0;
     // descriptor offsets, then the residue planes (offsets relative to off_planes) and the
     // product planes (offsets relative to off_ybytes)
-    size_t off_sjobs = 0, off_items = 0, off_cjobs = 0, off_planes = 0, off_ybytes = 0, bytes = 0;
+    size_t off_sjobs = 0, off_items = 0, off_cjobs = 0, off_counters = 0, off_planes = 0, off_ybytes = 0, bytes = 0;
 };
 
 hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint64_t *primes, int L,
@@ -458,6 +458,8 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
     off = align_up(off + lay.items.size() * sizeof(CrtItem), 256);
     lay.off_cjobs = off;
     off = align_up(off + lay.cjobs.size() * sizeof(CrtCombineJob), 256);
+    lay.off_counters = off;
+    off = align_up(off + kMaxChunks * sizeof(unsigned int), 256);
     lay.off_planes = off;
     lay.off_ybytes = align_up(off + plane_off, 256);
     lay.bytes = lay.off_ybytes + y_off;
@@ -497,12 +499,16 @@ hlb_status enqueue_crt(const CrtBatchLayout &lay, char *base, hipStream_t s) {
         CrtBatchArgs a;
         std::memset(&a, 0, sizeof(a));
         a.items = (const CrtItem *)(base + lay.off_items);
+        a.counters = (unsigned int *)(base + lay.off_counters);
         a.total_items = lay.total_items;
         a.D = lay.D;
         a.n_xcd = lay.n_chunks;
         for (int c = 0; c <= lay.n_chunks; ++c) a.chunk[c] = lay.chunk[c];
+        int n_xcd = 8, cus = 256;
+        (void)device_ready(&n_xcd, &cus);
+        if (launch_reset_counter(a.counters, s) != hipSuccess) return HLB_EDEVICE;
         ProfScope ps("crt_gemm_batch", s);
-        if (launch_crt_gemm_batch(a, s) != hipSuccess) return HLB_EDEVICE;
+        if (launch_crt_gemm_batch(a, cus, s) != hipSuccess) return HLB_EDEVICE;
     }
     ProfScope ps("crt_combine_batch", s);
     if (launch_crt_combine_batch((const CrtCombineJob *)(base + lay.off_cjobs), (int)lay.cjobs.size(), lay.combine_wgs,

@@ -1,7 +1,8 @@
 // crt_jobs.hpp -- residue arithmetic and job structures of the multimodular (CRT) form's
-// splits and recombination (crt.hip): the int8 residue of a value modulo each small modulus,
-// the recombination arguments of an output matrix, and the job tables that let one launch
-// split many operands or recombine many output matrices.
+// splits and recombination (crt.hip) and of its batch GEMM (crt_gemm_batch.hip): the int8
+// residue of a value modulo each small modulus, the recombination arguments of an output
+// matrix, the job tables that let one launch split many operands or recombine many output
+// matrices, and the host-resolved tiles of a batch.
 #pragma once
 
 #include <stdint.h>
@@ -103,6 +104,31 @@ struct CrtCombineTable {
 // Factors applied to the left operand's residues in the split: (M / p_i)^{-1} mod p_i.
 struct CrtScale {
     int32_t s[kCrtMaxModuli];
+};
+
+// One GEMM tile of a multimodular batch, resolved on the host: the first plane blocks of its
+// left and right operands for its modulus (k block 0), its k blocks, the modulus, and for
+// each of its 128-column plane tiles the product plane that tile writes (blocks per plane
+// row, block-column base) or none (null Y).  A tile may straddle the output matrices of one
+// problem, which lie side by side in plane tiles, or reach past the last of them.
+constexpr int kCrtItemCols = 3;  // plane tiles per batch GEMM tile (384 columns)
+struct CrtItem {
+    const int8_t *P;
+    const int8_t *X;
+    uint8_t *Y[kCrtItemCols];
+    int64_t nbc[kCrtItemCols];
+    int32_t bct[kCrtItemCols];
+    int32_t kblocks, p, brt;
+};
+
+// The items are cut into n_xcd contiguous runs of about equal cost (items differ in K), run x
+// being [chunk[x], chunk[x + 1]); XCD x serves run x first, then helps with the others.
+struct CrtBatchArgs {
+    const CrtItem *items;
+    unsigned int *counters;  // one per run, zeroed before each launch: items taken so far
+    int64_t total_items;
+    int32_t D, n_xcd;
+    int64_t chunk[kMaxChunks + 1];
 };
 
 }  // namespace hlb

@@ -1,0 +1,266 @@
+// crt_tile.hpp -- the output tile of the multimodular (CRT) INT8 products on gfx950: one
+// exact INT8 -> INT32 matrix product per small modulus (v_mfma_i32_32x32x32_i8) over a tile
+// of the residue planes written by the splits, with the epilogue that reduces each product
+// modulo its modulus and stores y_i = c mod p_i in the accumulator order of the product
+// planes (crt.hpp).  Strategy 3 of Section 6.1 in its FLINT variant.  Used by the GEMM of
+// one call (crt_gemm.hip) and by the batch GEMM (crt_gemm_batch.hip).
+#pragma once
+
+#include "common.hpp"
+#include "crt.hpp"
+
+namespace hlb {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------------------------------
+// One INT8 product per modulus on a 256 x BN output tile: WM x WN waves, each owning
+//    MB x NB blocks of 32 x 32 outputs (WM * MB * 32 = 256).  Variants (tile, waves, block
+//    per wave): 256 x 128 with 8 waves of 64 x 64; 256 x 256 with 8 waves of 64 x 128;
+//    256 x 384 with 8 waves of 128 x 96 (the default: 24 MFMAs per wave and stage, the most
+//    that two waves per SIMD can hold accumulators for, with 12% fewer LDS bytes per MFMA than
+//    64 x 128).  (Four waves of 128 x 128 need their 256 accumulators in AGPRs and leave one
+//    wave per SIMD, which hides less latency: measured slower.)
+// ---------------------------------------------------------------------------------------
+constexpr int kCrtBM = 256;
+constexpr int kCrtSub = kCrtR * kBK8;  // bytes of one plane block (128 x 64)
+
+// A stage holds only MB * NB MFMAs per wave and K half, so several stages must be in flight
+// to cover the load latency: as many as fit in the 160 KB of LDS.
+template <int MB_, int NB_, int WM_, int WN_>
+struct CrtTile {
+    static constexpr int MB = MB_, NB = NB_, WM = WM_, WN = WN_;
+    static_assert(WM * MB * 32 == kCrtBM, "256 rows per tile");
+    static constexpr int THREADS = 64 * WM * WN;
+    static constexpr int BN = WN * NB * 32;
+    static constexpr int XSUB = BN / kCrtR;            // residue plane blocks per stage
+    static constexpr int STAGE = (2 + XSUB) * kCrtSub;  // two plaintext blocks + residue blocks
+    static constexpr int GROUP = 2;                      // stages per barrier
+    static constexpr int NBUF = (160 * 1024) / STAGE / GROUP * GROUP;
+};
+using CrtNarrow = CrtTile<2, 2, 4, 2>;
+using CrtWide = CrtTile<2, 4, 4, 2>;
+using CrtWider = CrtTile<4, 3, 2, 4>;
+
+// c mod p in [0, p) for any int32 c and p <= 256: with c = h 2^16 + l (h signed, 0 <= l <
+// 2^16), u = h (2^16 mod p) + l satisfies |u| < 2^24, so u and the quotient estimate
+// floor(u / p) are exact in single precision up to one unit, which one correction each way
+// removes.  Integer products stay below 2^24 (24-bit multiply-adds).
+__device__ __forceinline__ uint32_t crt_y(int c, int p, int c16, float pinv) {
+    const int u = (c >> 16) * c16 + (c & 0xffff);
+    const int t = (int)__builtin_floorf((float)u * pinv);
+    int r = u - t * p;
+    r = r < 0 ? r + p : r;
+    r = r >= p ? r - p : r;
+    return (uint32_t)r;
+}
+
+// Where the 32-column block column bc of a tile goes: the product-plane block of its first
+// block row (1 KiB per 32 x 32 block) and the bytes from one block row to the next; null p
+// for a column outside every output.
+struct CrtBlockCol {
+    uint8_t *p;
+    int64_t row_bytes;
+};
+
+// One 256 x BN output tile of one modulus: the K loop over the plane blocks at gP (left, two
+// 128-row blocks tile_stride apart) and gX (right, XSUB 128-column blocks), then the epilogue,
+// which stores block column bc at dst(bc) (a wave-uniform CrtBlockCol).
+template <class T, class Dst>
+__device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const int8_t *gX, int KB, int64_t plane_stride,
+                                         int p, const Dst &dst) {
+    constexpr int MB = T::MB, NB = T::NB, kCrtThreads = T::THREADS, kCrtWavesN = T::WN;
+    constexpr int kCrtNbuf = T::NBUF;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave_u / kCrtWavesN, wn = wave_u % kCrtWavesN;
+    const int64_t tile_stride = (int64_t)KB * plane_stride;  // bytes of one 128-wide tile
+
+    v16i acc[MB][NB];
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = v16i{0};
+
+    constexpr int CH = kCrtSub / 16;  // 16-byte chunks per block
+    // the buffer form of the direct-to-LDS load (byte offsets within a tile's panels stay
+    // below 2^32: at most 3 x 2048 k blocks x 16 moduli x 8 KiB)
+    const __amdgpu_buffer_rsrc_t rsP = lds_src_rsrc(gP), rsX = lds_src_rsrc(gX);
+    auto gload = [&](int kb, int buf) {
+        int8_t *dst = lds + buf * T::STAGE;
+        const uint32_t off = (uint32_t)kb * (uint32_t)plane_stride;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+            copy_to_lds_buf<kCrtThreads, CH>(rsP, (uint32_t)(b * tile_stride) + off, dst + b * kCrtSub, tid, wave_u);
+#pragma unroll
+        for (int b = 0; b < T::XSUB; ++b)
+            copy_to_lds_buf<kCrtThreads, CH>(rsX, (uint32_t)(b * tile_stride) + off, dst + (2 + b) * kCrtSub, tid, wave_u);
+    };
+    const int loads_per_stage = (2 + T::XSUB) * loads_of_wave<kCrtThreads, CH>(wave_u);
+
+    // plaintext rows of this wave: wm * 32 MB + 32 mb + lane % 32, in 128-row block psub;
+    // residue columns: wn * 32 NB + 32 nb + lane % 32, in block (that) / 128
+    const int psub = (wm * 32 * MB) / kCrtR;
+    const int prow0 = (wm * 32 * MB) % kCrtR;
+    struct Frags {
+        v4i a[MB], b[NB];
+    };
+    // the fragments of row block mb / column block nb for K half kk of the stage in buffer buf
+    auto frag_a = [&](int buf, int kk, int mb) -> v4i {
+        const int8_t *lp = lds + buf * T::STAGE + psub * kCrtSub;
+        const int c = kk * 2 + (lane >> 5);
+        const int r = prow0 + mb * 32 + (lane & 31);
+        return *(const v4i *)(lp + r * 64 + ((c ^ swz(r)) << 4));
+    };
+    auto frag_b = [&](int buf, int kk, int nb) -> v4i {
+        const int8_t *lx = lds + buf * T::STAGE + 2 * kCrtSub;
+        const int c = kk * 2 + (lane >> 5);
+        const int col = wn * 32 * NB + nb * 32 + (lane & 31);
+        const int r = col & (kCrtR - 1);
+        return *(const v4i *)(lx + (col / kCrtR) * kCrtSub + r * 64 + ((c ^ swz(r)) << 4));
+    };
+    auto read_frags = [&](Frags &f, int buf, int kk) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) f.a[mb] = frag_a(buf, kk, mb);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) f.b[nb] = frag_b(buf, kk, nb);
+    };
+    auto mfmas = [&](const Frags &f) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a[mb], f.b[nb], acc[mb][nb], 0, 0, 0);
+    };
+
+    // Pipeline: half a stage of fragments in registers, NBUF stages in LDS, and one wait +
+    // barrier per group of G stages.  At a group's last half-stage each wave waits for its
+    // own loads of the whole next group, the barrier makes them visible (and tells that every
+    // wave has finished reading this group's buffers), and those buffers are refilled NBUF
+    // stages ahead.
+    constexpr int G = T::GROUP;
+    auto outstanding = [&](int need_hi, int issued_hi) {
+        const int ahead = min(KB - 1, issued_hi) - min(KB - 1, need_hi);
+        return ahead > 0 ? ahead * loads_per_stage : 0;
+    };
+#pragma unroll
+    for (int st = 0; st < kCrtNbuf; ++st)
+        if (st < KB) gload(st, st);
+    wait_vmcnt(outstanding(G - 1, kCrtNbuf - 1));
+    stage_barrier();
+    if constexpr (MB * NB >= 12) {
+        // One half-stage of fragments in registers, refilled in place: the MFMAs of a half run
+        // column block by column block (nb outer), so b[nb] is dead after its MB MFMAs and each
+        // a[mb] after its use in the last column block; each register set is refilled with the
+        // next half's fragment as soon as it dies, and the next half starts with the fragments
+        // refilled first.  Only the first half after each workgroup barrier waits for all of
+        // its reads.  Full groups of G stages run branch-free; a last partial group takes the
+        // plain schedule.
+        static_assert(G == 2, "four halves per group");
+        // the MFMAs of one half from f; with NEXT, refill f from (nbuf, nkk) as registers die
+        auto half = [&](Frags &f, bool next, int nbuf, int nkk) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    acc[mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a[mb], f.b[nb], acc[mb][nb], 0, 0, 0);
+                    if (next) {
+                        if (nb < NB - 1 && mb == MB - 1) f.b[nb] = frag_b(nbuf, nkk, nb);
+                        if (nb == NB - 1) {
+                            f.a[mb] = frag_a(nbuf, nkk, mb);
+                            if (mb == MB - 1) f.b[nb] = frag_b(nbuf, nkk, nb);
+                        }
+                    }
+                }
+            }
+            if (next) {
+                // pin the order: MB MFMAs then one read per column block but the last, then
+                // one read after each MFMA of the last column block (two after the final one)
+#pragma unroll
+                for (int nb = 0; nb < NB - 1; ++nb) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, MB, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                }
+#pragma unroll
+                for (int mb = 0; mb < MB - 1; ++mb) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        const int KBfull = KB - KB % G;
+        Frags f;
+#pragma unroll 1
+        for (int kb = 0; kb < KBfull; kb += G) {
+            const int b0 = kb % kCrtNbuf, b1 = (kb + 1) % kCrtNbuf;
+            read_frags(f, b0, 0);
+            half(f, true, b0, 1);
+            half(f, true, b1, 0);
+            half(f, true, b1, 1);
+            half(f, false, 0, 0);
+            wait_lds_after_mfmas();
+            wait_vmcnt(outstanding(kb + 2 * G - 1, kb + kCrtNbuf - 1));
+            stage_barrier();
+#pragma unroll
+            for (int h = 0; h < G; ++h)
+                if (kb + h + kCrtNbuf < KB) gload(kb + h + kCrtNbuf, (kb + h) % kCrtNbuf);
+        }
+        if (KBfull < KB) {
+            const int cur = KBfull % kCrtNbuf;
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                read_frags(f, cur, kk);
+                mfmas(f);
+            }
+        }
+    } else {
+        Frags f0, f1;
+        read_frags(f0, 0, 0);
+#pragma unroll 1
+        for (int kb = 0; kb < KB; kb += G) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int st = kb + g;
+                if (st >= KB) break;
+                const int cur = st % kCrtNbuf;
+                read_frags(f1, cur, 1);
+                mfmas(f0);
+                interleave_reads_with_mfmas<MB + NB>();
+                if (g == G - 1 || st + 1 == KB) {
+                    wait_lds_after_mfmas();
+                    // stages issued so far: up to kb + NBUF - 1; the next group must have landed
+                    wait_vmcnt(outstanding(kb + 2 * G - 1, kb + kCrtNbuf - 1));
+                    stage_barrier();
+#pragma unroll
+                    for (int h = 0; h < G; ++h)
+                        if (kb + h + kCrtNbuf < KB) gload(kb + h + kCrtNbuf, (kb + h) % kCrtNbuf);
+                }
+                if (st + 1 < KB) read_frags(f0, (st + 1) % kCrtNbuf, 0);
+                mfmas(f1);
+            }
+        }
+    }
+
+    // epilogue: one 16-byte store per 32 x 32 block and lane
+    const int c16 = (1 << 16) % p;
+    const float pinv = 1.0f / (float)p;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const CrtBlockCol col = dst(wn * NB + nb);
+        if (!col.p) continue;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int r = 0; r < 16; ++r) w[r >> 2] |= crt_y(acc[mb][nb][r], p, c16, pinv) << (8 * (r & 3));
+            *(uint4 *)(col.p + (wm * MB + mb) * col.row_bytes + lane * 16) = uint4{w[0], w[1], w[2], w[3]};
+        }
+    }
+}
+
+}  // namespace hlb

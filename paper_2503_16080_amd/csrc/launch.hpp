@@ -69,7 +69,8 @@ struct CrtCombineJob;
 hipError_t launch_crt_split_batch(int D, const CrtSplitJob *jobs, int njobs, int64_t total_wgs, const CrtScale &scale,
                                   hipStream_t s);
 int crt_batch_tile_cols();
-hipError_t launch_crt_gemm_batch(const CrtBatchArgs &a, hipStream_t s);
+// persistent: `workers` workgroups (at most one per CU fits), counters zeroed beforehand
+hipError_t launch_crt_gemm_batch(const CrtBatchArgs &a, int workers, hipStream_t s);
 int64_t crt_combine_wgs(int64_t m, int64_t n);
 hipError_t launch_crt_combine_batch(const CrtCombineJob *jobs, int njobs, int64_t total_wgs, hipStream_t s);
 // The same two with the job tables in the kernel arguments (at most kCrtTabSplit operands /
