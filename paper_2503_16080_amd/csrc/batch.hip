@@ -397,16 +397,17 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
         plane_off += (size_t)((tb + xsub - 1) * kblocks * sub);
         const int64_t items = (int64_t)D * tiles_m * tg;
         if (lay.total_items + items > INT32_MAX) return HLB_EINVAL;
-        // the problem's tiles: D moduli as D row bands of a (D tiles_m) x tg grid, walked
-        // group_m row tiles at a time, column by column (neighbours share operand panels);
-        // offsets are rebased once the workspace exists (kNoPlane marks a plane tile past the
-        // problem's outputs)
-        const int64_t tile_stride = kblocks * sub, tm_all = (int64_t)D * tiles_m, group_m = 4;
+        // the problem's tiles, modulus by modulus (tiles of different moduli share no operand
+        // bytes), each modulus's tiles_m x tg grid walked group_m row tiles at a time, column
+        // by column (neighbours share operand panels; measured 1.7 % faster on the 64-problem
+        // batch than groups of 4 row bands across moduli); offsets are rebased once the
+        // workspace exists (kNoPlane marks a plane tile past the problem's outputs)
+        const int64_t tile_stride = kblocks * sub, group_m = 8;
         for (int64_t local = 0; local < items; ++local) {
-            const int64_t span = group_m * tg, gi = local / span, first = gi * group_m;
-            const int64_t gm = std::min(group_m, tm_all - first), in = local - gi * span;
-            const int64_t rbv = first + in % gm, cb = in / gm;
-            const int64_t mi = rbv / tiles_m, rb = rbv % tiles_m;
+            const int64_t per_mod = tiles_m * tg, mi = local / per_mod, lm = local % per_mod;
+            const int64_t span = group_m * tg, gi = lm / span, first = gi * group_m;
+            const int64_t gm = std::min(group_m, tiles_m - first), in = lm - gi * span;
+            const int64_t rb = first + in % gm, cb = in / gm;
             CrtItem it;
             std::memset(&it, 0, sizeof(it));
             it.P = (const int8_t *)(uintptr_t)(p_off + (size_t)(2 * rb * tile_stride + mi * 128 * kBK8));

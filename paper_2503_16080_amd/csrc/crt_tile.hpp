@@ -43,17 +43,25 @@ using CrtNarrow = CrtTile<2, 2, 4, 2>;
 using CrtWide = CrtTile<2, 4, 4, 2>;
 using CrtWider = CrtTile<4, 3, 2, 4>;
 
-// c mod p in [0, p) for any int32 c and p <= 256: with c = h 2^16 + l (h signed, 0 <= l <
-// 2^16), u = h (2^16 mod p) + l satisfies |u| < 2^24, so u and the quotient estimate
-// floor(u / p) are exact in single precision up to one unit, which one correction each way
-// removes.  Integer products stay below 2^24 (24-bit multiply-adds).
+// c mod p in [0, p) for any int32 c and p <= 256, in twelve full-rate operations:
+//  * c = h 2^16 + l (h signed, 0 <= l < 2^16): u = h (2^16 mod p) + l = c (mod p) with
+//    |u| < 2^23 + 2^16, one 24-bit multiply-add (|h| < 2^15, 2^16 mod p < 2^8);
+//  * u is exact in single precision, and t = floor(u (1/p)) is within one of floor(u / p):
+//    the product carries a relative error below 2^-23, so an absolute one below 2^-6;
+//  * r = u - t p is formed exactly by one fused multiply-add (the exact value, in [-p, 2p),
+//    is representable) and brought into [0, p) by two unsigned minima:
+//    min(r, r + p) maps [-p, 0) to [0, p), and min(r, r - p) maps [p, 2p) to [0, p) (the other
+//    operand wraps to a large unsigned value).
 __device__ __forceinline__ uint32_t crt_y(int c, int p, int c16, float pinv) {
-    const int u = (c >> 16) * c16 + (c & 0xffff);
-    const int t = (int)__builtin_floorf((float)u * pinv);
-    int r = u - t * p;
-    r = r < 0 ? r + p : r;
-    r = r >= p ? r - p : r;
-    return (uint32_t)r;
+    // the 24-bit multiply-add written out: left to itself the compiler picks the quarter-rate
+    // 64-bit multiply-add here
+    int u;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(u) : "v"(c >> 16), "v"(c16), "v"(c & 0xffff));
+    const float uf = (float)u;
+    const float tf = __builtin_floorf(uf * pinv);
+    const int r = (int)__builtin_fmaf(-tf, (float)p, uf);
+    const uint32_t r1 = min((uint32_t)r, (uint32_t)(r + p));
+    return min(r1, r1 - (uint32_t)p);
 }
 
 // Where the 32-column block column bc of a tile goes: the product-plane block of its first
