@@ -34,7 +34,9 @@ __global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_batch_kernel(const Crt
             *next = t < args.chunk[run + 1] ? t : -1;
         }
         __syncthreads();
-        const int64_t t = *next;
+        // uniform (an LDS value is taken as per-lane otherwise): the tile's branches, loop
+        // bounds and addresses stay scalar
+        const int64_t t = __builtin_amdgcn_readfirstlane((int)*next);
         __syncthreads();  // every wave has read it before the tile's loads overwrite it
         if (t < 0) {
             run = run + 1 == args.n_xcd ? 0 : run + 1;
