@@ -68,6 +68,10 @@ def _parse():
     ap.add_argument("--summarize-mfma", metavar="PMC_DIR",
                     help="write the matrix-pipe summary of each GEMM kernel from one rocprofv3 --pmc "
                          "run of SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE and exit")
+    ap.add_argument("--hbm-reference", action="store_true",
+                    help="print the HBM rates of plain torch kernels (copy, fill, sum of 2 GiB) "
+                         "as one JSON line and exit: the practical ceiling of the HBM-bound "
+                         "splits and recombinations")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run 3 device-to-device copies of 1 GiB (a reference kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -199,6 +203,33 @@ def summarize_counters(fetch_dir, write_dir, d, L, kernel):
     with open(traffic_file(kernel, d, L), "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
+    return out
+
+
+def hbm_reference(reps=10):
+    """HBM rates of plain torch kernels on 2 GiB tensors, timed with events: a device copy
+    (read + write), a fill (write only) and a sum (read only)."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.int64, device="cuda:0")
+    y = torch.empty_like(x)
+    nbytes = x.numel() * 8
+
+    def ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = {"tensor_bytes": nbytes}
+    for name, fn, moved in (("copy", lambda: y.copy_(x), 2 * nbytes), ("fill", lambda: y.fill_(3), nbytes),
+                            ("sum", lambda: x.sum(), nbytes)):
+        t = ms(fn)
+        out[name] = {"ms": t, "tbs": moved / (t * 1e-3) / 1e12}
     return out
 
 
@@ -549,8 +580,10 @@ def main():
                 print(json.dumps(out))
         return
     if args.summarize_mfma:
+        tag = "batch64" if args.workload == "batch" else args.d
+        L = 4 if args.workload == "batch" else args.primes
         for kernel in TRAFFIC:
-            out = summarize_mfma(args.summarize_mfma, args.d, args.primes, kernel)
+            out = summarize_mfma(args.summarize_mfma, tag, L, kernel)
             if out is not None:
                 print(json.dumps(out))
         return
@@ -564,6 +597,10 @@ def main():
 
     import paper_2503_16080_amd as hlb
     import workloads as wl
+
+    if args.hbm_reference:
+        print(json.dumps(hbm_reference()), flush=True)
+        return
 
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.int64, device="cuda:0").fill_(1)
