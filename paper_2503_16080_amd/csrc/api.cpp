@@ -298,8 +298,9 @@ hlb_status plan(int kind, int64_t k, uint64_t qmax, int64_t pmax, int form, Plan
     if (form == HLB_FORM_INT8_CRT) return plan_crt(kind, k, qmax, pmax, pl);
     if (form == HLB_FORM_AUTO) {
         // the multimodular form when its D int8 products clearly undercut the digit pairs
-        // (both measured at d = 8192: 11 moduli at 38 % of the int8 peak beat 21 digit pairs
-        // at 50 %); the digit form otherwise, FP64 where no int8 plan exists
+        // (both measured at d = 8192: 11 moduli at 48-50 % of the int8 peak beat 21 digit
+        // pairs at 50 %, 1.7x faster per CP-MM); the digit form otherwise, FP64 where no int8
+        // plan exists
         Plan digit, crt;
         digit.kind = crt.kind = kind;
         const bool has_digit = plan_i8(kind, k, qmax, pmax, &digit) == HLB_OK;
@@ -353,7 +354,7 @@ static int tune_lookup(int dx, int64_t m, int64_t n, int64_t k) {
     return it == g_tune.end() ? -1 : it->second;
 }
 
-// AUTO picks the multimodular form by depth alone; its 256 x 256 output tiles would be mostly
+// AUTO picks the multimodular form by depth alone; its 256 x 384 output tiles would be mostly
 // padding on a small product, so there the digit plan is taken instead.
 static void auto_for_shape(Plan *pl, int form, int64_t m, int64_t n, int64_t k, uint64_t qmax, int64_t pmax) {
     if (form != HLB_FORM_AUTO || pl->form != HLB_FORM_INT8_CRT || (m >= 256 && n >= 256)) return;
