@@ -572,6 +572,8 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
                                    const std::vector<RightSpec> &rights, int64_t k, int n_xcd, hipStream_t s) {
     const int D = pl.np;
     const int wide = g_crt_wide.load();
+    int cus = 256;
+    (void)device_ready(nullptr, &cus);
     const int64_t bn = crt_tile_cols(wide), xsub = bn / 128;
     const int64_t kblocks = (k + kBK8 - 1) / kBK8;
     const int64_t sub = (int64_t)D * 128 * kBK8;  // bytes of one 128-wide tile and k block
@@ -608,17 +610,19 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
             }
     }
 
-    void *wsP = nullptr, *wsX = nullptr, *wsY = nullptr;
+    void *wsP = nullptr, *wsX = nullptr, *wsY = nullptr, *wsC = nullptr;
     WsLease lease;
     {
-        const size_t sizes[3] = {(size_t)(t128_m * kblocks * sub), (size_t)((tn_total + xsub - 1) * kblocks * sub),
-                                 (size_t)ybytes};
-        void *ptrs[3];
-        const hlb_status st = lease.take(s, sizes, ptrs, 3);
+        // planes of the left and right operands, product planes, tile-queue counters
+        const size_t sizes[4] = {(size_t)(t128_m * kblocks * sub), (size_t)((tn_total + xsub - 1) * kblocks * sub),
+                                 (size_t)ybytes, kMaxChunks * sizeof(unsigned int)};
+        void *ptrs[4];
+        const hlb_status st = lease.take(s, sizes, ptrs, 4);
         if (st != HLB_OK) return st;
         wsP = ptrs[0];
         wsX = ptrs[1];
         wsY = ptrs[2];
+        wsC = ptrs[3];
     }
     // offsets of each right operand's split tiles (128 wide) and product planes
     std::vector<int64_t> x_tile0(rights.size()), y_off(rights.size());
@@ -713,6 +717,7 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
         // 4 right operand panels (measured at d = 8192: 2, 4, 8, 16 -> 34.6, 32.8, 32.0, 33.2 ms)
         a.group_m = 8;
         a.n_xcd = n_xcd;
+        a.counters = (unsigned int *)wsC;
         int32_t tb = 0;
         for (size_t i = first; i < last; ++i) {
             CrtSeg &sg = a.seg[a.nseg++];
@@ -723,7 +728,7 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
         a.tiles_n = (int32_t)((tb + xsub - 1) / xsub);
         if (tb == 0) return true;
         ProfScope ps("crt_gemm", st);
-        return launch_crt_gemm(wide, a, st) == hipSuccess;
+        return launch_crt_gemm(wide, a, cus, st) == hipSuccess;
     };
     // Recombinations go out in launches of up to kCrtTabCombine output matrices.
     CrtCombineTable ctab;

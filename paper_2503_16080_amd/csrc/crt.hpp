@@ -48,6 +48,7 @@ struct CrtGemmArgs {
     int32_t tiles_n;     // GEMM column tiles (128, 256 or 384 wide) over all segments, which
                          // may straddle two segments
     int32_t group_m, n_xcd, nseg, pad;
+    unsigned int *counters;  // kMaxChunks tile-queue counters of a persistent launch, or null
     CrtSeg seg[kMaxSegs];
 };
 

@@ -2,8 +2,9 @@
 // exact INT8 -> INT32 matrix product per small modulus (v_mfma_i32_32x32x32_i8) over a tile
 // of the residue planes written by the splits, with the epilogue that reduces each product
 // modulo its modulus and stores y_i = c mod p_i in the accumulator order of the product
-// planes (crt.hpp).  Strategy 3 of Section 6.1 in its FLINT variant.  Used by the GEMM of
-// one call (crt_gemm.hip) and by the batch GEMM (crt_gemm_batch.hip).
+// planes (crt.hpp).  Strategy 3 of Section 6.1 in its FLINT variant.  crt_tile runs one tile
+// (one workgroup per tile, and the items of the batch GEMM, crt_gemm_batch.hip); crt_tiles runs
+// the stream of tiles of a persistent workgroup (the GEMM of one call, crt_gemm.hip).
 #pragma once
 
 #include "common.hpp"
@@ -268,6 +269,256 @@ __device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const in
             for (int r = 0; r < 16; ++r) w[r >> 2] |= crt_y(acc[mb][nb][r], p, c16, pinv) << (8 * (r & 3));
             *(uint4 *)(col.p + (wm * MB + mb) * col.row_bytes + lane * 16) = uint4{w[0], w[1], w[2], w[3]};
         }
+    }
+}
+
+// One output tile of one modulus: its plane blocks (left at gP, two 128-row blocks one
+// tile_stride = KB plane_stride apart; right at gX, XSUB 128-column blocks), its K blocks and
+// modulus, and where its products go (c0..c2, read by the sequence's dst).
+struct CrtRef {
+    const int8_t *gP, *gX;
+    int KB, p;
+    int64_t c0, c1, c2;
+};
+
+// The tiles of a persistent workgroup of 256 x 384 tiles, run as one stream of stages through
+// the LDS ring: the last groups of a tile load the first stages of the next, so that a tile's
+// epilogue and its product-byte stores overlap the next tile's loads and no tile starts with
+// an empty pipeline.  Every tile must have an even K-block count of at least NBUF.  The
+// workgroup takes its tiles one at a time from a queue; a queue Seq provides
+//   uint32_t claim();                  thread 0: start taking the next tile (a returning atomic)
+//   int resolve(uint32_t claimed);     thread 0: the tile claimed, or -1 once none is left
+//   CrtRef ref(int t) const;           tile t (wave-uniform t)
+//   CrtBlockCol dst(const CrtRef &, int bc) const;  where its 32-column block column bc goes
+// The claimed index reaches the other waves through LDS, at a barrier where a buffer is free.
+template <class T, class Seq>
+__device__ __forceinline__ void crt_tiles(int8_t *lds, int64_t plane_stride, Seq &seq) {
+    constexpr int MB = T::MB, NB = T::NB, kCrtThreads = T::THREADS, kCrtWavesN = T::WN;
+    constexpr int kCrtNbuf = T::NBUF;
+    constexpr int G = T::GROUP;
+    static_assert(MB * NB >= 12 && G == 2 && kCrtNbuf == 2 * G, "the rolling schedule over a ring of two groups");
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave_u / kCrtWavesN, wn = wave_u % kCrtWavesN;
+
+    // the tile index from thread 0 to every wave, through the first bytes of LDS buffer buf
+    // (free: no wave reads it and no load into it is in flight)
+    auto broadcast = [&](int buf, int t0) -> int {
+        int *slot = (int *)(lds + buf * T::STAGE);  // ordered by the barriers' memory clobbers
+        if (tid == 0) *slot = t0;
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        stage_barrier();
+        const int t = __builtin_amdgcn_readfirstlane(*slot);
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        stage_barrier();  // every wave has read it before loads overwrite it
+        return t;
+    };
+
+    v16i acc[MB][NB];
+    auto zero_acc = [&]() {
+#pragma unroll
+        for (int a = 0; a < MB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[a][b] = v16i{0};
+    };
+
+    constexpr int CH = kCrtSub / 16;  // 16-byte chunks per block
+    // a tile's sources for the buffer form of the direct-to-LDS load, in scalar registers
+    // (byte offsets within a tile's panels stay below 2^32: at most 3 x 2048 k blocks x 16
+    // moduli x 8 KiB)
+    struct Src {
+        __amdgpu_buffer_rsrc_t rsP, rsX;
+        uint32_t tile_stride;  // bytes of one 128-wide tile
+    };
+    auto source = [&](const CrtRef &r) -> Src {
+        return Src{lds_src_rsrc(r.gP), lds_src_rsrc(r.gX),
+                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(r.KB * plane_stride))};
+    };
+    // stage kb of a tile into LDS buffer buf
+    auto gload = [&](const Src &src, int kb, int buf) {
+        int8_t *dst = lds + buf * T::STAGE;
+        const uint32_t off = (uint32_t)kb * (uint32_t)plane_stride;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+            copy_to_lds_buf<kCrtThreads, CH>(src.rsP, b * src.tile_stride + off, dst + b * kCrtSub, tid, wave_u);
+#pragma unroll
+        for (int b = 0; b < T::XSUB; ++b)
+            copy_to_lds_buf<kCrtThreads, CH>(src.rsX, b * src.tile_stride + off, dst + (2 + b) * kCrtSub, tid, wave_u);
+    };
+    const int loads_per_stage = (2 + T::XSUB) * loads_of_wave<kCrtThreads, CH>(wave_u);
+
+    // plaintext rows of this wave: wm * 32 MB + 32 mb + lane % 32, in 128-row block psub;
+    // residue columns: wn * 32 NB + 32 nb + lane % 32, in block (that) / 128
+    const int psub = (wm * 32 * MB) / kCrtR;
+    const int prow0 = (wm * 32 * MB) % kCrtR;
+    struct Frags {
+        v4i a[MB], b[NB];
+    };
+    // the fragments of row block mb / column block nb for K half kk of the stage in buffer buf
+    auto frag_a = [&](int buf, int kk, int mb) -> v4i {
+        const int8_t *lp = lds + buf * T::STAGE + psub * kCrtSub;
+        const int c = kk * 2 + (lane >> 5);
+        const int r = prow0 + mb * 32 + (lane & 31);
+        return *(const v4i *)(lp + r * 64 + ((c ^ swz(r)) << 4));
+    };
+    auto frag_b = [&](int buf, int kk, int nb) -> v4i {
+        const int8_t *lx = lds + buf * T::STAGE + 2 * kCrtSub;
+        const int c = kk * 2 + (lane >> 5);
+        const int col = wn * 32 * NB + nb * 32 + (lane & 31);
+        const int r = col & (kCrtR - 1);
+        return *(const v4i *)(lx + (col / kCrtR) * kCrtSub + r * 64 + ((c ^ swz(r)) << 4));
+    };
+    auto read_frags = [&](Frags &f, int buf, int kk) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) f.a[mb] = frag_a(buf, kk, mb);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) f.b[nb] = frag_b(buf, kk, nb);
+    };
+
+    // epilogue: one 16-byte store per 32 x 32 block and lane; returns the stores issued
+    auto epilogue = [&](const CrtRef &r) -> int {
+        const int p = r.p;
+        const int c16 = (1 << 16) % p;
+        const float pinv = 1.0f / (float)p;
+        int stores = 0;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const CrtBlockCol col = seq.dst(r, wn * NB + nb);
+            if (!col.p) continue;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int e = 0; e < 16; ++e) w[e >> 2] |= crt_y(acc[mb][nb][e], p, c16, pinv) << (8 * (e & 3));
+                *(uint4 *)(col.p + (wm * MB + mb) * col.row_bytes + lane * 16) = uint4{w[0], w[1], w[2], w[3]};
+            }
+            stores += MB;
+        }
+        return stores;
+    };
+
+    // One half-stage of fragments in registers, refilled in place: the MFMAs of a half run
+    // column block by column block (nb outer), so b[nb] is dead after its MB MFMAs and each
+    // a[mb] after its use in the last column block; each register set is refilled with the
+    // next half's fragment as soon as it dies, and the next half starts with the fragments
+    // refilled first.  Only the first half after each workgroup barrier waits for all of its
+    // reads.
+    auto half = [&](Frags &f, bool next, int nbuf, int nkk) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                acc[mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a[mb], f.b[nb], acc[mb][nb], 0, 0, 0);
+                if (next) {
+                    if (nb < NB - 1 && mb == MB - 1) f.b[nb] = frag_b(nbuf, nkk, nb);
+                    if (nb == NB - 1) {
+                        f.a[mb] = frag_a(nbuf, nkk, mb);
+                        if (mb == MB - 1) f.b[nb] = frag_b(nbuf, nkk, nb);
+                    }
+                }
+            }
+        }
+        if (next) {
+            // pin the order: MB MFMAs then one read per column block but the last, then one
+            // read after each MFMA of the last column block (two after the final one)
+#pragma unroll
+            for (int nb = 0; nb < NB - 1; ++nb) {
+                __builtin_amdgcn_sched_group_barrier(0x008, MB, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+#pragma unroll
+            for (int mb = 0; mb < MB - 1; ++mb) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+
+    // Stage s of the stream sits in buffer s mod NBUF.  The loads of a group are issued one
+    // group ahead of their use, so a group's wait covers every load but those issued since:
+    // the last tile's epilogue stores (vmcnt counts loads and stores in issue order) and, at
+    // a tile's first wait, the loads of its stages 2 and 3.
+    int t = broadcast(0, tid == 0 ? seq.resolve(seq.claim()) : 0);
+    if (t < 0) return;
+    CrtRef cur = seq.ref(t);
+    Src cs = source(cur);
+#pragma unroll
+    for (int st = 0; st < kCrtNbuf; ++st) gload(cs, st, st);
+    wait_vmcnt(2 * loads_per_stage);
+    stage_barrier();
+    int ring = 0, stores = 0;
+    Frags f;
+#pragma unroll 1
+    while (true) {
+        // the claim of the next tile goes out now and is read back near the tile's end
+        uint32_t claimed = 0;
+        if (tid == 0) claimed = seq.claim();
+        bool more = false;
+        CrtRef nxt = cur;
+        Src ns = cs;
+        zero_acc();
+        const int KB = cur.KB;
+        // all groups but the last two: their successors are stages of this tile
+#pragma unroll 1
+        for (int kb = 0; kb < KB - 2 * G; kb += G) {
+            const int b0 = (ring + kb) % kCrtNbuf, b1 = (ring + kb + 1) % kCrtNbuf;
+            read_frags(f, b0, 0);
+            half(f, true, b0, 1);
+            half(f, true, b1, 0);
+            half(f, true, b1, 1);
+            half(f, false, 0, 0);
+            wait_lds_after_mfmas();
+            if (kb == 0) wait_vmcnt(stores);
+            else wait_vmcnt(0);
+            stage_barrier();
+#pragma unroll
+            for (int h = 0; h < G; ++h) gload(cs, kb + h + kCrtNbuf, (ring + kb + h) % kCrtNbuf);
+        }
+        // the last two groups: the next tile is learnt, and its first stages loaded
+#pragma unroll 1
+        for (int kb = KB - 2 * G; kb < KB; kb += G) {
+            const int b0 = (ring + kb) % kCrtNbuf, b1 = (ring + kb + 1) % kCrtNbuf;
+            read_frags(f, b0, 0);
+            half(f, true, b0, 1);
+            half(f, true, b1, 0);
+            half(f, true, b1, 1);
+            half(f, false, 0, 0);
+            wait_lds_after_mfmas();
+            if (kb + G < KB || more) {
+                // the next group's stages have landed: they were issued before the last tile's
+                // stores (at a tile's first wait) or are the last loads issued
+                if (kb == 0) wait_vmcnt(stores);
+                else wait_vmcnt(0);
+                stage_barrier();
+                if (kb == KB - 2 * G) {
+                    // buffers b0, b1 are free: learn the next tile before loading its stages
+                    const int tn = broadcast(b0, tid == 0 ? seq.resolve(claimed) : 0);
+                    if (tn >= 0) {
+                        more = true;
+                        nxt = seq.ref(tn);
+                        ns = source(nxt);
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < G; ++h) {
+                    const int s = kb + h + kCrtNbuf, buf = (ring + kb + h) % kCrtNbuf;
+                    if (s < KB) gload(cs, s, buf);
+                    else if (more) gload(ns, s - KB, buf);
+                }
+            }
+        }
+        stores = epilogue(cur);
+        if (!more) return;
+        ring = (ring + KB) % kCrtNbuf;
+        cur = nxt;
+        cs = ns;
+        // the next tile's stages 0 and 1: issued before its stages 2, 3 and the stores
+        wait_vmcnt(2 * loads_per_stage + stores);
+        stage_barrier();
     }
 }
 

@@ -56,10 +56,10 @@ int crt_round_d(int D);  // smallest supported D >= D, or 0
 struct CrtScale;
 struct CrtGemmArgs;
 struct CrtCombineArgs;
-// variant 0: 256 x 128 output tiles; 1: 256 x 256; 2: 256 x 384 (the default; all 8 waves).
-// crt_tile_cols gives the tile width.
+// variant 0: 256 x 128 output tiles; 1: 256 x 256 (both 8 waves).  crt_tile_cols gives the
+// tile width.
 int crt_tile_cols(int variant);
-hipError_t launch_crt_gemm(int variant, const CrtGemmArgs &a, hipStream_t s);
+hipError_t launch_crt_gemm(int variant, const CrtGemmArgs &a, int workers, hipStream_t s);
 // Batched forms: one launch for many operands (jobs in increasing wg_start), one GEMM launch
 // for many problems (256 x crt_batch_tile_cols() tiles), one launch for many recombinations
 // (crt_combine_wgs workgroups each).
