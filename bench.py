@@ -82,8 +82,9 @@ _CSRC = os.path.join(ROOT, "paper_2503_16080_amd", "csrc")
 # Counter summaries per GEMM kernel: the sources whose SHA-256 they are valid for, and the
 # kernel-name substring that selects their dispatches.  One file per kernel and workload.
 TRAFFIC = {
+    # the persistent launch (every benchmark size has an even K-block count of at least four)
     "crt_gemm": {"sources": [os.path.join(_CSRC, f) for f in ("crt_gemm.hip", "crt_tile.hpp", "crt.hpp", "common.hpp")],
-                 "match": "crt_gemm_kernel"},
+                 "match": "crt_gemm_stream_kernel"},
     "gemm_i8": {"sources": [os.path.join(_CSRC, f) for f in ("gemm_i8.hip", "i8_tile.hpp", "common.hpp")],
                 "match": "gemm_i8_kernel"},
     "gemm_f64": {"sources": [os.path.join(_CSRC, f) for f in ("gemm_f64_planes.hip", "common.hpp")],
