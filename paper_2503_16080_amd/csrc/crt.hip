@@ -64,7 +64,10 @@ __device__ __forceinline__ void crt_store_planes(const CrtValue (&x)[16], int8_t
             }
             w[q4] = crt_pack4(b[0], b[1], b[2], b[3]);
         }
-        *(uint4 *)(dst + I * kCrtR * 64) = uint4{w[0], w[1], w[2], w[3]};
+        // streaming (non-temporal) stores: the planes are far larger than the caches, and the
+        // GEMM that reads them is not slower for it (the split 2-3 % faster)
+        typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(v4u{w[0], w[1], w[2], w[3]}, (v4u *)(dst + I * kCrtR * 64));
         crt_store_planes<I + 1, D, SCALED>(x, dst, scale);
     }
 }
@@ -230,7 +233,8 @@ __device__ __forceinline__ void crt_combine_lane(const CrtCombineArgs &a, const 
         const uint64_t sum = ((uint64_t)s2[e] << 40) + ((uint64_t)s1[e] << 20) + s0[e];
         const uint64_t sr = reduce_u64(sum, a.q, a.barrett);
         const uint64_t tm = tmq[(int)__builtin_floorf(f[e] + 0.5f)];
-        a.C[row * a.ldc + col] = sr >= tm ? sr - tm : sr + a.q - tm;
+        // streaming store: the outputs are not read again here
+        __builtin_nontemporal_store(sr >= tm ? sr - tm : sr + a.q - tm, &a.C[row * a.ldc + col]);
     }
 }
 
