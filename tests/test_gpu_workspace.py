@@ -70,13 +70,17 @@ def test_release_between_calls():
         hlb.release()
 
 
-@pytest.mark.parametrize("form", FORMS)
-def test_caller_captures_cp_mm_in_a_graph(form):
+# (300, 700, 260, 2): 11 K blocks, one GEMM workgroup per tile; (600, 640, 700, 2): 10 K
+# blocks and 264 tiles, the persistent multimodular launch (a queue-counter fill kernel, then
+# workgroups taking several tiles each)
+@pytest.mark.parametrize("form,shape", [(f, (300, 700, 260, 2)) for f in FORMS] + [("int8_crt", (600, 640, 700, 2))])
+def test_caller_captures_cp_mm_in_a_graph(form, shape):
     # under capture the workspace is a graph-owned allocation; every replay, with eager work
     # and synchronisations between replays, matches the oracle
-    w, want = _case(60, (300, 700, 260, 2))
+    m, k, n, L = shape
+    w, want = _case(60, shape)
     P, A, B = _t(w.P), _t(w.A), _t(w.B)
-    PA = torch.empty((2, 300, 260), dtype=torch.int64, device=DEV)
+    PA = torch.empty((L, m, n), dtype=torch.int64, device=DEV)
     PB = torch.empty_like(PA)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())

@@ -30,9 +30,10 @@ def _np(t):
 
 @pytest.mark.parametrize("form", FORMS)
 def test_noalloc_matches_cp_mm_on_consecutive_calls(form):
-    # a larger problem, then a smaller one over fewer primes: the second call reuses the array
-    # that still holds the first call's planes
-    for i, (m, k, n, L) in enumerate([(700, 900, 520, 3), (130, 257, 75, 2)]):
+    # larger problems, then a smaller one over fewer primes: each call reuses the array that
+    # still holds the last call's planes (the first, with 6 K blocks and 704 tiles, runs the
+    # persistent multimodular GEMM, whose queue counters also live in the array)
+    for i, (m, k, n, L) in enumerate([(1024, 384, 1024, 3), (700, 900, 520, 3), (130, 257, 75, 2)]):
         print(f"\n[noalloc] form={form} call {i}: m={m} k={k} n={n} L={L}", flush=True)
         w = wl.cpmm_uniform(9300 + i, m, k, n, 50, L)
         P, A, B = _t(w.P), _t(w.A), _t(w.B)
