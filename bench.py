@@ -324,6 +324,10 @@ def batch_leg(steps, warmup, loops=True):
     import workloads as wl
 
     seed, L, bits = 1004, 4, 45
+    # the multimodular batch's tile classes, from the autotuner's table for this workload
+    tune_table = os.path.join(ROOT, "paper_2503_16080_amd", "tune_crt_batch64_mi355x.txt")
+    if os.path.exists(tune_table):
+        hlb.hlb_tune_load(tune_table)
     primes, shapes, probs = wl.batch_problems_device(seed, 64, bits, L)
     dev = torch.device("cuda:0")
     macs = 0
@@ -354,15 +358,22 @@ def batch_leg(steps, warmup, loops=True):
     s_crt = _time_steps(batch("int8_crt"), steps, warmup)
     s_digit = _time_steps(batch("int8"), steps, warmup)
     crt_moduli = hlb.plan(1, max(d for _, d in shapes), max(primes), 1 << 20, "int8_crt")["p_limbs"]
+    classes = [hlb.hlb_tune_class_crt(crt_moduli, m, d, d) for m, d in shapes]
+    # the batch GEMM per step: one launch per tile class present
+    n_g, ms_g = kb["crt_gemm_batch"]
+    gemm_step_ms = ms_g * n_g / steps
     out = {
         "value": macs / s_crt, "unit": "mod-q MAC/s", "ms_per_step": s_crt * 1e3,
         "workload": "64 CP-MMs, d log-uniform [128, 4096], m log-uniform [64, 4096], n = d, 4 primes of "
                     "45 bits, multimodular INT8 form, one graph-replayed batch call",
         "moduli": crt_moduli, "mod_q_macs": macs,
-        "roofline": _roofline("crt_gemm_batch", kb["crt_gemm_batch"][0], kb["crt_gemm_batch"][1],
+        "roofline": _roofline("crt_gemm_batch", steps, gemm_step_ms,
                               2.0 * crt_moduli * macs, steps, "batch64", L, INT8_PEAK_TOPS, "TOP/s",
                               "int8 MAC x 2 (useful products only)"),
-        "kernels_ms": {n: v[1] for n, v in kb.items()},
+        "kernels_ms": {n: v[1] * v[0] / steps for n, v in kb.items()},
+        "tile_classes": {"table": os.path.basename(tune_table) if os.path.exists(tune_table) else None,
+                         "problems_per_class": {str(c): classes.count(c) for c in sorted(set(classes))},
+                         "gemm_launches_per_step": n_g / steps},
         "eager_batch_ms": s_crt_eager * 1e3,
         "digit_form": {"value": macs / s_digit, "ms": s_digit * 1e3, "digits": [3, 6],
                        "eager_ms": s_digit_eager * 1e3},

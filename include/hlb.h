@@ -275,9 +275,11 @@ typedef enum {
                                  operands into double planes (library workspace), then the
                                  direct-to-LDS GEMM; 0 = the register-staged kernel, which
                                  needs no workspace.  Results are identical. */
-    HLB_OPT_CRT_WIDE = 6,     /* multimodular GEMM tile: 2 (default) = 256 x 384 outputs,
-                                 1 = 256 x 256, 0 = 256 x 128; other values are refused with
-                                 HLB_EINVAL.  Results are identical. */
+    HLB_OPT_CRT_WIDE = 6,     /* multimodular GEMM tile class: -1 (default) = per problem
+                                 from the tuning table (256 x 384 where it has no entry);
+                                 2 = 256 x 384 outputs, 1 = 256 x 256, 0 = 256 x 128 force a
+                                 class for every call and batch problem; other values are
+                                 refused with HLB_EINVAL.  Results are identical. */
     HLB_OPT_WS_CAP = 7        /* > 0: refuse any single stream-ordered workspace allocation
                                  above this many bytes with HLB_ENOMEM, before any launch
                                  that would use it (a host-side way to exercise the
@@ -302,6 +304,21 @@ hlb_status hlb_set_option(int option, int64_t value);
 hlb_status hlb_tune_set(int x_digits, int log2m, int log2n, int log2k, int cls);
 hlb_status hlb_tune_load(const char *path);
 int hlb_tune_class(int x_digits, int64_t m, int64_t n, int64_t k);
+
+/*
+ * The same table for the multimodular form (host only).  Its GEMM has three workgroup tile
+ * classes: 0 = 256 x 128, 1 = 256 x 256, 2 = 256 x 384 outputs.  The planner picks one per
+ * single call and per problem of a batch (a batch runs one persistent GEMM launch per class
+ * present), keyed by the moduli count D and the floor(log2) of m, n (of one output matrix)
+ * and k; class 2 where the table has no entry; HLB_OPT_CRT_WIDE >= 0 overrides it.
+ *   hlb_tune_set_crt:   sets one entry (cls 0, 1 or 2; cls -1 erases it); HLB_EINVAL for
+ *                       D outside 1..16, log2 fields outside 0..63 or another class.
+ *   hlb_tune_load:      also reads entries "crt D log2m log2n log2k cls".
+ *   hlb_tune_class_crt: the class the planner would use for a shape (-1 for invalid
+ *                       arguments).
+ */
+hlb_status hlb_tune_set_crt(int moduli, int log2m, int log2n, int log2k, int cls);
+int hlb_tune_class_crt(int moduli, int64_t m, int64_t n, int64_t k);
 
 /*
  * Kernel timing collected while HLB_OPT_PROFILE is on (synchronous: waits for the

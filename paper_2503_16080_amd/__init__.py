@@ -24,6 +24,7 @@ __all__ = [
     "hlb_plaintext_absmax", "hlb_plan", "hlb_set_option", "hlb_profile_read",
     "hlb_profile_reset", "hlb_release", "hlb_status_str", "hlb_test_encode",
     "hlb_test_encrypt", "hlb_test_decrypt", "hlb_tune_set", "hlb_tune_load", "hlb_tune_class",
+    "hlb_tune_set_crt", "hlb_tune_class_crt",
     "hlb_ccmm_pp_core", "hlb_rescale", "ccmm_pp_core", "rescale",
     "mod_pp_mm", "cp_mm", "cp_mm_noalloc", "cp_mm_batch", "validate_residues", "plaintext_absmax", "plan",
     "set_option", "profile_read", "profile_reset", "release",
@@ -109,6 +110,8 @@ def load():
             "hlb_tune_set": (ci, [ci, ci, ci, ci, ci]),
             "hlb_tune_load": (ci, [ctypes.c_char_p]),
             "hlb_tune_class": (ci, [ci, i64, i64, i64]),
+            "hlb_tune_set_crt": (ci, [ci, ci, ci, ci, ci]),
+            "hlb_tune_class_crt": (ci, [ci, i64, i64, i64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -423,6 +426,16 @@ def hlb_tune_load(path: str):
 def hlb_tune_class(x_digits: int, m: int, n: int, k: int) -> int:
     """INT8 tile class the planner picks for an m x n (one output matrix) x k problem."""
     return int(load().hlb_tune_class(int(x_digits), int(m), int(n), int(k)))
+
+
+def hlb_tune_set_crt(moduli: int, log2m: int, log2n: int, log2k: int, cls: int):
+    _check(load().hlb_tune_set_crt(int(moduli), int(log2m), int(log2n), int(log2k), int(cls)), "tune_set_crt")
+
+
+def hlb_tune_class_crt(moduli: int, m: int, n: int, k: int) -> int:
+    """Multimodular tile class (0: 256 x 128, 1: 256 x 256, 2: 256 x 384 outputs) the planner
+    picks for an m x n (one output matrix) x k problem over `moduli` moduli."""
+    return int(load().hlb_tune_class_crt(int(moduli), int(m), int(n), int(k)))
 
 
 # ------------------------------------------------------------------------------------------

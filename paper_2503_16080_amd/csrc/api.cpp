@@ -31,7 +31,7 @@ static std::atomic<int> g_profile{0};
 static std::atomic<int> g_batch_graph{1};
 static std::atomic<int> g_force_class{-1};
 static std::atomic<int> g_f64_planes{1};
-static std::atomic<int> g_crt_wide{2};
+static std::atomic<int> g_crt_wide{-1};  // -1: the tuned class per shape
 static std::atomic<int64_t> g_ws_cap{0};
 
 int64_t opt_force_kchunk() { return g_force_kchunk.load(); }
@@ -330,6 +330,11 @@ static uint32_t tune_key(int dx, int lm, int ln, int lk) {
     return ((uint32_t)(dx & 0xff) << 24) | ((uint32_t)(lm & 0x3f) << 12) | ((uint32_t)(ln & 0x3f) << 6) |
            (uint32_t)(lk & 0x3f);
 }
+// Multimodular entries share the table under the first key field 0x80 | moduli count.
+static uint32_t tune_key_crt(int moduli, int lm, int ln, int lk) { return tune_key(0x80 | moduli, lm, ln, lk); }
+static bool tune_fields_ok(int lm, int ln, int lk) {
+    return lm >= 0 && lm <= 63 && ln >= 0 && ln <= 63 && lk >= 0 && lk <= 63;
+}
 static hlb_status tune_load_locked(const char *path) {
     FILE *f = std::fopen(path, "r");
     if (!f) return HLB_EINVAL;
@@ -337,8 +342,13 @@ static hlb_status tune_load_locked(const char *path) {
     while (std::fgets(line, sizeof(line), f)) {
         if (line[0] == '#') continue;
         int dx, lm, ln, lk, c;
-        if (std::sscanf(line, "%d %d %d %d %d", &dx, &lm, &ln, &lk, &c) == 5 && (c == 0 || c == 1))
+        if (std::sscanf(line, " crt %d %d %d %d %d", &dx, &lm, &ln, &lk, &c) == 5) {
+            if (dx >= 1 && dx <= kCrtMaxModuli && tune_fields_ok(lm, ln, lk) && c >= 0 && c <= 2)
+                g_tune[tune_key_crt(dx, lm, ln, lk)] = c;
+        } else if (std::sscanf(line, "%d %d %d %d %d", &dx, &lm, &ln, &lk, &c) == 5 && dx >= 1 && dx <= 8 &&
+                   tune_fields_ok(lm, ln, lk) && (c == 0 || c == 1)) {
             g_tune[tune_key(dx, lm, ln, lk)] = c;
+        }
     }
     std::fclose(f);
     return HLB_OK;
@@ -352,6 +362,16 @@ static int tune_lookup(int dx, int64_t m, int64_t n, int64_t k) {
     }
     auto it = g_tune.find(tune_key(dx, floor_log2(m), floor_log2(n), floor_log2(k)));
     return it == g_tune.end() ? -1 : it->second;
+}
+
+// The multimodular GEMM's tile class for a product of D moduli, m rows, n columns (of one
+// output matrix) and depth k: the forced class (HLB_OPT_CRT_WIDE), else the tuned one, else
+// 256 x 384 (2), the widest, which holds the most MFMAs per wave and stage.
+int crt_tile_class(int D, int64_t m, int64_t n, int64_t k) {
+    const int forced = g_crt_wide.load();
+    if (forced >= 0) return forced;
+    const int c = tune_lookup(0x80 | D, std::max<int64_t>(m, 1), std::max<int64_t>(n, 1), std::max<int64_t>(k, 1));
+    return c >= 0 ? c : 2;
 }
 
 // AUTO picks the multimodular form by depth alone; its 256 x 384 output tiles would be mostly
@@ -571,7 +591,10 @@ void ws_release_all() {
 static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &lefts,
                                    const std::vector<RightSpec> &rights, int64_t k, int n_xcd, hipStream_t s) {
     const int D = pl.np;
-    const int wide = g_crt_wide.load();
+    int64_t mmax0 = 0, nmax0 = 0;
+    for (const LeftSpec &L : lefts) mmax0 = std::max(mmax0, L.m);
+    for (const RightSpec &R : rights) nmax0 = std::max(nmax0, R.n);
+    const int wide = crt_tile_class(D, mmax0, nmax0, k);
     int cus = 256;
     (void)device_ready(nullptr, &cus);
     const int64_t bn = crt_tile_cols(wide), xsub = bn / 128;
@@ -1279,7 +1302,7 @@ hlb_status hlb_set_option(int option, int64_t value) {
             g_f64_planes.store(value ? 1 : 0);
             return HLB_OK;
         case HLB_OPT_CRT_WIDE:
-            if (value < 0 || value > 2) return HLB_EINVAL;
+            if (value < -1 || value > 2) return HLB_EINVAL;
             g_crt_wide.store((int)value);
             return HLB_OK;
         case HLB_OPT_WS_CAP:
@@ -1326,6 +1349,21 @@ hlb_status hlb_tune_set(int x_digits, int log2m, int log2n, int log2k, int cls) 
     if (cls < 0) g_tune.erase(key);
     else g_tune[key] = cls;
     return HLB_OK;
+}
+
+hlb_status hlb_tune_set_crt(int moduli, int log2m, int log2n, int log2k, int cls) {
+    if (moduli < 1 || moduli > kCrtMaxModuli || !tune_fields_ok(log2m, log2n, log2k) || cls < -1 || cls > 2)
+        return HLB_EINVAL;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    const uint32_t key = tune_key_crt(moduli, log2m, log2n, log2k);
+    if (cls < 0) g_tune.erase(key);
+    else g_tune[key] = cls;
+    return HLB_OK;
+}
+
+int hlb_tune_class_crt(int moduli, int64_t m, int64_t n, int64_t k) {
+    if (moduli < 1 || moduli > kCrtMaxModuli || m < 1 || n < 1 || k < 1) return -1;
+    return crt_tile_class(moduli, m, n, k);
 }
 
 hlb_status hlb_tune_load(const char *path) {

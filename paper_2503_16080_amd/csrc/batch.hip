@@ -257,21 +257,28 @@ hlb_status enqueue(const BatchLayout &lay, char *base, int grid, hipStream_t s) 
 // Marks, before rebasing, a batch GEMM tile's plane tile that lies past its problem's outputs.
 constexpr uintptr_t kNoPlane = ~(uintptr_t)0;
 
+// The GEMM items of one tile class: their own persistent launch, runs and queue counters.
+struct CrtClassItems {
+    std::vector<CrtItem> items;
+    int64_t chunk[kMaxChunks + 1] = {0};
+    size_t off_items = 0, off_counters = 0;
+};
+
 struct CrtBatchLayout {
     int D = 0;
     CrtScale scale;
     std::vector<CrtSplitJob> sjobs;
     int64_t split_wgs = 0;
-    std::vector<CrtItem> items;
+    CrtClassItems cls[kCrtClasses];
+    std::vector<int> prob_cls;  // tile class of every non-empty problem, in problem order
     int n_chunks = 1;
-    int64_t chunk[kMaxChunks + 1] = {0};
     std::vector<CrtSeg> segs;
     std::vector<CrtCombineJob> cjobs;
     int64_t combine_wgs = 0;
     int64_t total_items = 0;
     // descriptor offsets, then the residue planes (offsets relative to off_planes) and the
     // product planes (offsets relative to off_ybytes)
-    size_t off_sjobs = 0, off_items = 0, off_cjobs = 0, off_counters = 0, off_planes = 0, off_ybytes = 0, bytes = 0;
+    size_t off_sjobs = 0, off_cjobs = 0, off_planes = 0, off_ybytes = 0, bytes = 0;
 };
 
 hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint64_t *primes, int L,
@@ -307,12 +314,21 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
     std::vector<int> order(count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].k > probs[b].k; });
-    const int64_t bn = crt_batch_tile_cols(), xsub = bn / 128;
     const int64_t sub = (int64_t)D * 128 * kBK8;  // bytes of one 128-wide tile and k block
+    // every problem's GEMM tile class (tuning table, or the forced class)
+    std::vector<int> pcls(count, -1);
+    for (int i = 0; i < count; ++i) {
+        const hlb_cpmm_problem &p = probs[i];
+        if (p.m == 0 || p.k == 0 || (p.nA == 0 && p.nB == 0)) continue;
+        pcls[i] = crt_tile_class(D, p.m, std::max(p.nA, p.nB), p.k);
+        lay.prob_cls.push_back(pcls[i]);
+    }
     size_t plane_off = 0, y_off = 0;
     for (int oi = 0; oi < count; ++oi) {
         const hlb_cpmm_problem &p = probs[order[oi]];
         if (p.m == 0 || p.k == 0 || (p.nA == 0 && p.nB == 0)) continue;
+        CrtClassItems &ci = lay.cls[pcls[order[oi]]];
+        const int64_t xsub = crt_tile_cols(pcls[order[oi]]) / 128;
         const int64_t kblocks = (p.k + kBK8 - 1) / kBK8;
         const int64_t lt = ((p.m + 255) / 256) * 2, tiles_m = lt / 2;
 
@@ -427,40 +443,43 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
             it.kblocks = (int32_t)kblocks;
             it.p = kCrtModuli[mi];
             it.brt = (int32_t)(rb * 8);
-            lay.items.push_back(it);
+            ci.items.push_back(it);
         }
         lay.total_items += items;
     }
     if (lay.total_items > INT32_MAX || lay.split_wgs > INT32_MAX || lay.combine_wgs > INT32_MAX) return HLB_EINVAL;
-    // one contiguous run of items per XCD, of about equal cost: an item costs its K blocks plus
-    // a fixed cost worth about twelve of them (pipeline fill, epilogue, launch; measured on the
-    // 64-problem batch: 2, 8, 12, 20 -> 22.8, 18.3, 16.2, 17.2 ms for the GEMM)
+    // per class, one contiguous run of items per XCD, of about equal cost: an item costs its K
+    // blocks plus a fixed cost worth about twelve of them (pipeline fill, epilogue, launch;
+    // measured on the 64-problem batch: 2, 8, 12, 20 -> 22.8, 18.3, 16.2, 17.2 ms for the GEMM)
     int n_xcd = 8;
     (void)device_ready(&n_xcd);
     lay.n_chunks = std::max(1, std::min(n_xcd, kMaxChunks));
-    double total_cost = 0.0;
     constexpr double kItemFixed = 12.0;
-    for (const CrtItem &it : lay.items) total_cost += it.kblocks + kItemFixed;
-    {
+    for (CrtClassItems &ci : lay.cls) {
+        const int64_t n_items = (int64_t)ci.items.size();
+        double total_cost = 0.0;
+        for (const CrtItem &it : ci.items) total_cost += it.kblocks + kItemFixed;
         int c = 1;
         double acc = 0.0;
-        for (int64_t i = 0; i < (int64_t)lay.items.size() && c < lay.n_chunks; ++i) {
-            acc += lay.items[i].kblocks + kItemFixed;
-            while (c < lay.n_chunks && acc >= total_cost * c / lay.n_chunks) lay.chunk[c++] = i + 1;
+        for (int64_t i = 0; i < n_items && c < lay.n_chunks; ++i) {
+            acc += ci.items[i].kblocks + kItemFixed;
+            while (c < lay.n_chunks && acc >= total_cost * c / lay.n_chunks) ci.chunk[c++] = i + 1;
         }
-        for (; c <= lay.n_chunks; ++c) lay.chunk[c] = lay.total_items;
-        lay.chunk[0] = 0;
-        lay.chunk[lay.n_chunks] = lay.total_items;
+        for (; c <= lay.n_chunks; ++c) ci.chunk[c] = n_items;
+        ci.chunk[0] = 0;
+        ci.chunk[lay.n_chunks] = n_items;
     }
     size_t off = 0;
     lay.off_sjobs = off;
     off = align_up(off + lay.sjobs.size() * sizeof(CrtSplitJob), 256);
-    lay.off_items = off;
-    off = align_up(off + lay.items.size() * sizeof(CrtItem), 256);
+    for (CrtClassItems &ci : lay.cls) {
+        ci.off_items = off;
+        off = align_up(off + ci.items.size() * sizeof(CrtItem), 256);
+        ci.off_counters = off;
+        off = align_up(off + kMaxChunks * sizeof(unsigned int), 256);
+    }
     lay.off_cjobs = off;
     off = align_up(off + lay.cjobs.size() * sizeof(CrtCombineJob), 256);
-    lay.off_counters = off;
-    off = align_up(off + kMaxChunks * sizeof(unsigned int), 256);
     lay.off_planes = off;
     lay.off_ybytes = align_up(off + plane_off, 256);
     lay.bytes = lay.off_ybytes + y_off;
@@ -471,24 +490,27 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
 void rebase_crt(CrtBatchLayout &lay, char *base) {
     char *planes = base + lay.off_planes, *ybytes = base + lay.off_ybytes;
     for (CrtSplitJob &j : lay.sjobs) j.out = (int8_t *)(planes + (uintptr_t)j.out);
-    for (CrtItem &it : lay.items) {
-        it.P = (const int8_t *)(planes + (uintptr_t)it.P);
-        it.X = (const int8_t *)(planes + (uintptr_t)it.X);
-        for (int j = 0; j < kCrtItemCols; ++j)
-            it.Y[j] = (uintptr_t)it.Y[j] == kNoPlane ? nullptr : (uint8_t *)(ybytes + (uintptr_t)it.Y[j]);
-    }
+    for (CrtClassItems &ci : lay.cls)
+        for (CrtItem &it : ci.items) {
+            it.P = (const int8_t *)(planes + (uintptr_t)it.P);
+            it.X = (const int8_t *)(planes + (uintptr_t)it.X);
+            for (int j = 0; j < kCrtItemCols; ++j)
+                it.Y[j] = (uintptr_t)it.Y[j] == kNoPlane ? nullptr : (uint8_t *)(ybytes + (uintptr_t)it.Y[j]);
+        }
     for (CrtCombineJob &j : lay.cjobs) j.a.Y = (const uint8_t *)(ybytes + (uintptr_t)j.a.Y);
 }
 
 std::vector<char> crt_descriptor_image(const CrtBatchLayout &lay) {
     std::vector<char> img(lay.off_planes, 0);
     std::memcpy(img.data() + lay.off_sjobs, lay.sjobs.data(), lay.sjobs.size() * sizeof(CrtSplitJob));
-    std::memcpy(img.data() + lay.off_items, lay.items.data(), lay.items.size() * sizeof(CrtItem));
+    for (const CrtClassItems &ci : lay.cls)
+        std::memcpy(img.data() + ci.off_items, ci.items.data(), ci.items.size() * sizeof(CrtItem));
     std::memcpy(img.data() + lay.off_cjobs, lay.cjobs.data(), lay.cjobs.size() * sizeof(CrtCombineJob));
     return img;
 }
 
-// The three launches of a multimodular batch on stream s (capturable: kernels only).
+// The launches of a multimodular batch on stream s (capturable: kernels only): the split,
+// one persistent GEMM per tile class present, the recombination.
 hlb_status enqueue_crt(const CrtBatchLayout &lay, char *base, hipStream_t s) {
     {
         ProfScope ps("crt_split_batch", s);
@@ -496,20 +518,22 @@ hlb_status enqueue_crt(const CrtBatchLayout &lay, char *base, hipStream_t s) {
                                    lay.split_wgs, lay.scale, s) != hipSuccess)
             return HLB_EDEVICE;
     }
-    {
+    int n_xcd = 8, cus = 256;
+    (void)device_ready(&n_xcd, &cus);
+    for (int c = kCrtClasses - 1; c >= 0; --c) {
+        const CrtClassItems &ci = lay.cls[c];
+        if (ci.items.empty()) continue;
         CrtBatchArgs a;
         std::memset(&a, 0, sizeof(a));
-        a.items = (const CrtItem *)(base + lay.off_items);
-        a.counters = (unsigned int *)(base + lay.off_counters);
-        a.total_items = lay.total_items;
+        a.items = (const CrtItem *)(base + ci.off_items);
+        a.counters = (unsigned int *)(base + ci.off_counters);
+        a.total_items = (int64_t)ci.items.size();
         a.D = lay.D;
         a.n_xcd = lay.n_chunks;
-        for (int c = 0; c <= lay.n_chunks; ++c) a.chunk[c] = lay.chunk[c];
-        int n_xcd = 8, cus = 256;
-        (void)device_ready(&n_xcd, &cus);
+        for (int x = 0; x <= lay.n_chunks; ++x) a.chunk[x] = ci.chunk[x];
         if (launch_reset_counter(a.counters, s) != hipSuccess) return HLB_EDEVICE;
         ProfScope ps("crt_gemm_batch", s);
-        if (launch_crt_gemm_batch(a, cus, s) != hipSuccess) return HLB_EDEVICE;
+        if (launch_crt_gemm_batch(c, a, cus, s) != hipSuccess) return HLB_EDEVICE;
     }
     ProfScope ps("crt_combine_batch", s);
     if (launch_crt_combine_batch((const CrtCombineJob *)(base + lay.off_cjobs), (int)lay.cjobs.size(), lay.combine_wgs,
@@ -560,16 +584,17 @@ std::vector<uint64_t> signature(const hlb_cpmm_problem *probs, int count, const 
     return sig;
 }
 
-// Key of a cached multimodular batch graph: a tag, device, stream, D, the primes and every
-// problem field.
+// Key of a cached multimodular batch graph: a tag, device, stream, D, every problem's tile
+// class, the primes and every problem field.
 std::vector<uint64_t> crt_signature(const hlb_cpmm_problem *probs, int count, const uint64_t *primes, int L, int dev,
-                                    hipStream_t s, int D) {
+                                    hipStream_t s, int D, const std::vector<int> &prob_cls) {
     std::vector<uint64_t> sig;
     sig.reserve((size_t)count * 11 + L + 8);
     sig.push_back(0x4352544241544348ull);  // distinguishes these keys from the digit batch's
     sig.push_back((uint64_t)dev);
     sig.push_back((uint64_t)(uintptr_t)s);
     sig.push_back((uint64_t)D);
+    for (int c : prob_cls) sig.push_back((uint64_t)c);
     sig.push_back((uint64_t)L);
     for (int l = 0; l < L; ++l) sig.push_back(primes[l]);
     for (int i = 0; i < count; ++i) {
@@ -605,7 +630,7 @@ hlb_status run_crt_batch(const hlb_cpmm_problem *probs, int count, const uint64_
     }
     int dev = 0;
     (void)hipGetDevice(&dev);
-    const std::vector<uint64_t> sig = crt_signature(probs, count, primes, L, dev, s, lay.D);
+    const std::vector<uint64_t> sig = crt_signature(probs, count, primes, L, dev, s, lay.D, lay.prob_cls);
     std::lock_guard<std::mutex> g(g_graph_mu);
     auto it = g_graphs.find(sig);
     if (it == g_graphs.end()) {

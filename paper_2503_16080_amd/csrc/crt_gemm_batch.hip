@@ -24,7 +24,7 @@ __global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_batch_kernel(const Crt
     __shared__ __attribute__((aligned(16))) int8_t lds[T::NBUF * T::STAGE];
     // the tile's pipeline fills all of LDS, so the item index passes through its first bytes
     volatile int64_t *next = (volatile int64_t *)lds;
-    static_assert(T::XSUB == kCrtItemCols, "one destination per plane tile of the batch tile");
+    static_assert(T::XSUB <= kCrtItemCols, "one destination per plane tile of the batch tile");
     int run = (int)(blockIdx.x % args.n_xcd);
     int exhausted = 0;
     while (exhausted < args.n_xcd) {
@@ -57,15 +57,21 @@ __global__ __launch_bounds__(T::THREADS, 1) void crt_gemm_batch_kernel(const Crt
 // ---------------------------------------------------------------------------------------
 // Launcher
 // ---------------------------------------------------------------------------------------
-hipError_t launch_crt_gemm_batch(const CrtBatchArgs &a, int workers, hipStream_t s) {
-    if (a.total_items <= 0) return hipSuccess;
-    if (a.n_xcd < 1 || a.n_xcd > kMaxChunks || a.total_items > INT32_MAX || workers < 1 || !a.counters)
-        return hipErrorInvalidValue;
+template <class T>
+static hipError_t launch_batch_t(const CrtBatchArgs &a, int workers, hipStream_t s) {
     const int64_t grid = std::min<int64_t>(workers, a.total_items);
-    hipLaunchKernelGGL(crt_gemm_batch_kernel<CrtWider>, dim3((unsigned)grid), dim3(CrtWider::THREADS), 0, s, a);
+    hipLaunchKernelGGL(crt_gemm_batch_kernel<T>, dim3((unsigned)grid), dim3(T::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
-int crt_batch_tile_cols() { return CrtWider::BN; }
+hipError_t launch_crt_gemm_batch(int variant, const CrtBatchArgs &a, int workers, hipStream_t s) {
+    if (a.total_items <= 0) return hipSuccess;
+    if (a.n_xcd < 1 || a.n_xcd > kMaxChunks || a.total_items > INT32_MAX || workers < 1 || !a.counters)
+        return hipErrorInvalidValue;
+    if (variant == 0) return launch_batch_t<CrtNarrow>(a, workers, s);
+    if (variant == 1) return launch_batch_t<CrtWide>(a, workers, s);
+    if (variant == 2) return launch_batch_t<CrtWider>(a, workers, s);
+    return hipErrorInvalidValue;
+}
 
 }  // namespace hlb

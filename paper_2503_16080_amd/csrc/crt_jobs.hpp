@@ -121,6 +121,10 @@ struct CrtItem {
     int32_t kblocks, p, brt;
 };
 
+// Tile classes of the multimodular GEMM (256 x 128, 256 x 256, 256 x 384 outputs); a batch
+// runs one persistent GEMM launch per class present.
+constexpr int kCrtClasses = 3;
+
 // The items are cut into n_xcd contiguous runs of about equal cost (items differ in K), run x
 // being [chunk[x], chunk[x + 1]); XCD x serves run x first, then helps with the others.
 struct CrtBatchArgs {

@@ -55,6 +55,10 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
 // Picks the INT8 tile class of a problem (m rows, n columns per output matrix, depth k) and
 // updates pl->cls / bm / bn accordingly; no-op for plans with a single class.
 void choose_class(Plan *pl, int64_t m, int64_t n, int64_t k);
+// The multimodular GEMM's tile class (0: 256 x 128, 1: 256 x 256, 2: 256 x 384 outputs) for D
+// moduli, m rows, n columns per output matrix and depth k: forced by HLB_OPT_CRT_WIDE, else
+// from the tuning table, else 2.
+int crt_tile_class(int D, int64_t m, int64_t n, int64_t k);
 int i8_digits_for(uint64_t vmax);
 hlb_status check_modulus(uint64_t q);
 hlb_status device_ready(int *n_xcd, int *cus = nullptr);

@@ -61,16 +61,15 @@ struct CrtCombineArgs;
 int crt_tile_cols(int variant);
 hipError_t launch_crt_gemm(int variant, const CrtGemmArgs &a, int workers, hipStream_t s);
 // Batched forms: one launch for many operands (jobs in increasing wg_start), one GEMM launch
-// for many problems (256 x crt_batch_tile_cols() tiles), one launch for many recombinations
-// (crt_combine_wgs workgroups each).
+// per tile class for many problems (256 x crt_tile_cols(variant) tiles), one launch for many
+// recombinations (crt_combine_wgs workgroups each).
 struct CrtSplitJob;
 struct CrtBatchArgs;
 struct CrtCombineJob;
 hipError_t launch_crt_split_batch(int D, const CrtSplitJob *jobs, int njobs, int64_t total_wgs, const CrtScale &scale,
                                   hipStream_t s);
-int crt_batch_tile_cols();
 // persistent: `workers` workgroups (at most one per CU fits), counters zeroed beforehand
-hipError_t launch_crt_gemm_batch(const CrtBatchArgs &a, int workers, hipStream_t s);
+hipError_t launch_crt_gemm_batch(int variant, const CrtBatchArgs &a, int workers, hipStream_t s);
 int64_t crt_combine_wgs(int64_t m, int64_t n);
 hipError_t launch_crt_combine_batch(const CrtCombineJob *jobs, int njobs, int64_t total_wgs, hipStream_t s);
 // The same two with the job tables in the kernel arguments (at most kCrtTabSplit operands /

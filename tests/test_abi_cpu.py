@@ -143,9 +143,9 @@ def test_entry_points_reject_bad_arguments_before_device_work():
     assert lib.hlb_set_option(999, 1) == 6
     assert lib.hlb_set_option(hlb.OPT_FORCE_KCHUNK, -5) == 1
     assert lib.hlb_set_option(hlb.OPT_F64_PLANES, 0) == 0 and lib.hlb_set_option(hlb.OPT_F64_PLANES, 1) == 0
-    for v in (0, 1, 2):
+    for v in (0, 1, 2, -1):
         assert lib.hlb_set_option(hlb.OPT_CRT_WIDE, v) == 0
-    assert lib.hlb_set_option(hlb.OPT_CRT_WIDE, 3) == 1 and lib.hlb_set_option(hlb.OPT_CRT_WIDE, -1) == 1
+    assert lib.hlb_set_option(hlb.OPT_CRT_WIDE, 3) == 1 and lib.hlb_set_option(hlb.OPT_CRT_WIDE, -2) == 1
     assert lib.hlb_set_option(hlb.OPT_WS_CAP, -1) == 1
     assert lib.hlb_set_option(hlb.OPT_WS_CAP, 1 << 20) == 0 and lib.hlb_set_option(hlb.OPT_WS_CAP, 0) == 0
 
@@ -190,6 +190,42 @@ def test_tile_class_heuristic_and_tuning_table(tmp_path):
         hlb.set_option(hlb.OPT_FORCE_CLASS, -1)
     with pytest.raises(hlb.HlbError):
         hlb.set_option(hlb.OPT_FORCE_CLASS, 2)
+
+
+def test_multimodular_tile_class_table(tmp_path):
+    # no entry: the widest class (256 x 384); entries per (moduli, log2 m, log2 n, log2 k)
+    assert hlb.hlb_tune_class_crt(10, 300, 1000, 1000) == 2
+    hlb.hlb_tune_set_crt(10, 8, 9, 9, 0)
+    try:
+        assert hlb.hlb_tune_class_crt(10, 300, 1000, 1000) == 0
+        assert hlb.hlb_tune_class_crt(11, 300, 1000, 1000) == 2   # another moduli count
+        assert hlb.hlb_tune_class_crt(10, 600, 1000, 1000) == 2   # another row bucket
+        # the digit form's entries live beside them without clashing
+        assert hlb.hlb_tune_class(7, 300, 1000, 1000) in (0, 1)
+        # a forced class overrides the table, -1 returns to it
+        hlb.set_option(hlb.OPT_CRT_WIDE, 1)
+        assert hlb.hlb_tune_class_crt(10, 300, 1000, 1000) == 1
+        hlb.set_option(hlb.OPT_CRT_WIDE, -1)
+        assert hlb.hlb_tune_class_crt(10, 300, 1000, 1000) == 0
+    finally:
+        hlb.set_option(hlb.OPT_CRT_WIDE, -1)
+        hlb.hlb_tune_set_crt(10, 8, 9, 9, -1)
+    assert hlb.hlb_tune_class_crt(10, 300, 1000, 1000) == 2
+    # the table file holds both kinds of lines
+    f = tmp_path / "tune.txt"
+    f.write_text("# comment\ncrt 10 6 7 7 1   # ms\n6 6 10 10 0\ncrt 99 6 7 7 1\ncrt 10 6 7 7 5\n")
+    hlb.hlb_tune_load(str(f))
+    try:
+        assert hlb.hlb_tune_class_crt(10, 100, 200, 200) == 1
+        assert hlb.hlb_tune_class(6, 64, 1024, 1024) == 0
+    finally:
+        hlb.hlb_tune_set_crt(10, 6, 7, 7, -1)
+        hlb.hlb_tune_set(6, 6, 10, 10, -1)
+    assert hlb.hlb_tune_class_crt(10, 100, 200, 200) == 2
+    for bad in ((0, 1, 1, 1, 0), (17, 1, 1, 1, 0), (10, 64, 1, 1, 0), (10, 1, 1, 1, 3), (10, 1, 1, 1, -2)):
+        with pytest.raises(hlb.HlbError):
+            hlb.hlb_tune_set_crt(*bad)
+    assert hlb.hlb_tune_class_crt(0, 1, 1, 1) == -1 and hlb.hlb_tune_class_crt(10, 0, 1, 1) == -1
 
 
 def test_trunc_b_planner_bounds():

@@ -42,7 +42,7 @@ def test_cp_mm_crt_vs_oracle(dims, wide):
         PA, PB = hlb.cp_mm(_t(w.P), _t(A), _t(B), w.primes, p_absmax=w.p_absmax, form="int8_crt")
         got = (_np(PA), _np(PB))
     finally:
-        hlb.set_option(hlb.OPT_CRT_WIDE, 2)
+        hlb.set_option(hlb.OPT_CRT_WIDE, -1)
     wantA, wantB = oracle.cp_mm(w.P, A, B, w.primes)
     assert np.array_equal(got[0], wantA) and np.array_equal(got[1], wantB)
 
@@ -233,3 +233,43 @@ def test_batch_multimodular_moduli_count_from_largest_member():
     hlb.cp_mm_batch(probs, primes, form="int8_crt")
     for p, (wA, wB) in zip(probs, want):
         assert np.array_equal(_np(p["PA"]), wA) and np.array_equal(_np(p["PB"]), wB)
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_batch_multimodular_tile_classes_from_the_table(graph):
+    # tuning-table entries give the members three different tile classes, so the batch runs
+    # one persistent GEMM launch per class; a forced class then overrides the table; every
+    # member exact each time
+    primes = wl.ntt_primes(45, 2, skip=1)
+    g = wl.rng(6000 + graph)
+    shapes = [(300, 200, 260), (600, 130, 400), (70, 520, 90), (1100, 64, 700)]
+    probs, want = [], []
+    for m, k, n in shapes:
+        P = wl.plaintext_matrix(g, m, k)
+        A = np.stack([wl.uniform_residues(g, (k, n), q) for q in primes])
+        B = np.stack([wl.uniform_residues(g, (k, n), q) for q in primes])
+        probs.append(dict(P=_t(P), A=_t(A), B=_t(B), p_absmax=1 << 20,
+                          PA=torch.empty((2, m, n), dtype=torch.int64, device=DEV),
+                          PB=torch.empty((2, m, n), dtype=torch.int64, device=DEV)))
+        want.append(oracle.cp_mm(P, A, B, primes))
+    D = hlb.plan(1, max(k for _, k, _ in shapes), max(primes), 1 << 20, "int8_crt")["p_limbs"]
+    keys = [(D, int(np.log2(m)), int(np.log2(n)), int(np.log2(k))) for m, k, n in shapes]
+    assert len(set(keys)) == len(keys)
+    hlb.set_option(hlb.OPT_BATCH_GRAPH, graph)
+    try:
+        for key, cls in zip(keys, (0, 1, 2, 0)):
+            hlb.hlb_tune_set_crt(*key, cls)
+        assert [hlb.hlb_tune_class_crt(D, m, n, k) for m, k, n in shapes] == [0, 1, 2, 0]
+        for forced in (-1, 1):
+            hlb.set_option(hlb.OPT_CRT_WIDE, forced)
+            for p in probs:
+                p["PA"].fill_(-1)
+                p["PB"].fill_(-1)
+            hlb.cp_mm_batch(probs, primes, form="int8_crt")
+            for j, (p, (wA, wB)) in enumerate(zip(probs, want)):
+                assert np.array_equal(_np(p["PA"]), wA) and np.array_equal(_np(p["PB"]), wB), (forced, j)
+    finally:
+        hlb.set_option(hlb.OPT_CRT_WIDE, -1)
+        hlb.set_option(hlb.OPT_BATCH_GRAPH, 1)
+        for key in keys:
+            hlb.hlb_tune_set_crt(*key, -1)
