@@ -78,6 +78,19 @@ def _parse():
     return ap.parse_args()
 
 
+# The paper's own CP-MM timings at the headline size (Table tab:pcmm, d1 = d2 = d3 = 2^13, in
+# its shared-a format: the a-part is 2^12 x d2), with the hardware and settings its text names:
+# context, not a target (another machine, one modulus, the b-part approximate).
+PAPER_FIGURES = {
+    "source": "Table tab:pcmm, 2^13 x 2^13 x 2^13 row",
+    "hardware": "Intel Xeon Gold 6342 @ 2.80 GHz, single thread; OpenBLAS 0.3.26 dgemm; HEaaN",
+    "a_part_s": 19.1, "b_part_s": 13.3, "total_s": 32.4,
+    "mod_q_macs": (1 << 12) * (1 << 13) * (1 << 13) + (1 << 39),
+    "setting": "one modulus of about 54 bits (no RNS), b-part approximate (Strategy 2), a-part "
+               "exact (Strategy 1, 3 FP64 products); average of 10 runs",
+}
+PAPER_FIGURES["mod_q_mac_per_s"] = PAPER_FIGURES["mod_q_macs"] / PAPER_FIGURES["total_s"]
+
 _CSRC = os.path.join(ROOT, "paper_2503_16080_amd", "csrc")
 # Counter summaries per GEMM kernel: the sources whose SHA-256 they are valid for, and the
 # kernel-name substring that selects their dispatches.  One file per kernel and workload.
@@ -718,6 +731,8 @@ def main():
         out["config5_d16384_int8"] = config5_leg(max(3, args.steps // 4), 1)
         out["config4_batch64"], _ = batch_leg(args.steps, args.warmup)
 
+    if d == 8192:
+        out["paper_figures"] = PAPER_FIGURES
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
 
