@@ -65,6 +65,22 @@ __device__ __forceinline__ uint32_t crt_y(int c, int p, int c16, float pinv) {
     return min(r1, r1 - (uint32_t)p);
 }
 
+// c mod p in [0, p) in six full-rate operations when |c| <= 2^28 (a product over at most
+// 2^14 of K, i.e. at most kCrtShortKB K blocks, of residues in [-128, 127]) and p >= 191 (every
+// modulus of the table):
+//  * x = c (1/p), with the conversion, the reciprocal and the product each rounded to
+//    nearest in single precision, is within 3 2^-24 |c / p| < 2^-2 of c / p;
+//  * so t = floor(x + 1/2) (one rounding conversion) is floor(c / p) or one more, and
+//    r = c - t p lies in [-p, p); |t| < 2^21, so one 24-bit multiply-add forms r exactly;
+//  * one unsigned minimum maps [-p, 0) to [0, p), as in crt_y.
+constexpr int kCrtShortKB = 256;
+__device__ __forceinline__ uint32_t crt_y_short(int c, int negp, float pinv) {
+    int t, r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(t) : "v"((float)c * pinv));
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(t), "v"(negp), "v"(c));
+    return min((uint32_t)r, (uint32_t)(r - negp));
+}
+
 // Where the 32-column block column bc of a tile goes: the product-plane block of its first
 // block row (1 KiB per 32 x 32 block) and the bytes from one block row to the next; null p
 // for a column outside every output.
@@ -72,6 +88,35 @@ struct CrtBlockCol {
     uint8_t *p;
     int64_t row_bytes;
 };
+
+// The epilogue of a wave: its MB x NB blocks of 32 x 32 products reduced modulo p (by
+// crt_y_short when SHORT, for tiles of at most kCrtShortKB K blocks; else by crt_y) and
+// stored, one 16-byte store per block and lane, block column bc at dst(bc) (a wave-uniform
+// CrtBlockCol).  Returns the stores issued.
+template <int MB, int NB, bool SHORT, class Dst>
+__device__ __forceinline__ int crt_epilogue(const v16i (&acc)[MB][NB], int p, int wm, int wn, int lane,
+                                            const Dst &dst) {
+    const int c16 = (1 << 16) % p;
+    const float pinv = 1.0f / (float)p;
+    int stores = 0;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const CrtBlockCol col = dst(wn * NB + nb);
+        if (!col.p) continue;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t y = SHORT ? crt_y_short(acc[mb][nb][e], -p, pinv) : crt_y(acc[mb][nb][e], p, c16, pinv);
+                w[e >> 2] |= y << (8 * (e & 3));
+            }
+            *(uint4 *)(col.p + (wm * MB + mb) * col.row_bytes + lane * 16) = uint4{w[0], w[1], w[2], w[3]};
+        }
+        stores += MB;
+    }
+    return stores;
+}
 
 // One 256 x BN output tile of one modulus: the K loop over the plane blocks at gP (left, two
 // 128-row blocks tile_stride apart) and gX (right, XSUB 128-column blocks), then the epilogue,
@@ -255,21 +300,8 @@ __device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const in
         }
     }
 
-    // epilogue: one 16-byte store per 32 x 32 block and lane
-    const int c16 = (1 << 16) % p;
-    const float pinv = 1.0f / (float)p;
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const CrtBlockCol col = dst(wn * NB + nb);
-        if (!col.p) continue;
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            uint32_t w[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-            for (int r = 0; r < 16; ++r) w[r >> 2] |= crt_y(acc[mb][nb][r], p, c16, pinv) << (8 * (r & 3));
-            *(uint4 *)(col.p + (wm * MB + mb) * col.row_bytes + lane * 16) = uint4{w[0], w[1], w[2], w[3]};
-        }
-    }
+    if (KB <= kCrtShortKB) crt_epilogue<MB, NB, true>(acc, p, wm, wn, lane, dst);
+    else crt_epilogue<MB, NB, false>(acc, p, wm, wn, lane, dst);
 }
 
 // One output tile of one modulus: its plane blocks (left at gP, two 128-row blocks one
@@ -375,26 +407,11 @@ __device__ __forceinline__ void crt_tiles(int8_t *lds, int64_t plane_stride, Seq
         for (int nb = 0; nb < NB; ++nb) f.b[nb] = frag_b(buf, kk, nb);
     };
 
-    // epilogue: one 16-byte store per 32 x 32 block and lane; returns the stores issued
+    // the epilogue of tile r; returns the stores issued
     auto epilogue = [&](const CrtRef &r) -> int {
-        const int p = r.p;
-        const int c16 = (1 << 16) % p;
-        const float pinv = 1.0f / (float)p;
-        int stores = 0;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const CrtBlockCol col = seq.dst(r, wn * NB + nb);
-            if (!col.p) continue;
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                uint32_t w[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-                for (int e = 0; e < 16; ++e) w[e >> 2] |= crt_y(acc[mb][nb][e], p, c16, pinv) << (8 * (e & 3));
-                *(uint4 *)(col.p + (wm * MB + mb) * col.row_bytes + lane * 16) = uint4{w[0], w[1], w[2], w[3]};
-            }
-            stores += MB;
-        }
-        return stores;
+        const auto dst = [&](int bc) { return seq.dst(r, bc); };
+        return r.KB <= kCrtShortKB ? crt_epilogue<MB, NB, true>(acc, r.p, wm, wn, lane, dst)
+                                   : crt_epilogue<MB, NB, false>(acc, r.p, wm, wn, lane, dst);
     };
 
     // One half-stage of fragments in registers, refilled in place: the MFMAs of a half run
@@ -440,8 +457,10 @@ __device__ __forceinline__ void crt_tiles(int8_t *lds, int64_t plane_stride, Seq
 
     // Stage s of the stream sits in buffer s mod NBUF.  The loads of a group are issued one
     // group ahead of their use, so a group's wait covers every load but those issued since:
-    // the last tile's epilogue stores (vmcnt counts loads and stores in issue order) and, at
-    // a tile's first wait, the loads of its stages 2 and 3.
+    // the last tile's epilogue stores and, at a tile's first wait, the loads of its stages 2
+    // and 3.  This rests on vmcnt counting the buffer loads and the epilogue's stores together
+    // and retiring them in issue order, as on gfx9 targets, which have no separate store
+    // counter.
     int t = broadcast(0, tid == 0 ? seq.resolve(seq.claim()) : 0);
     if (t < 0) return;
     CrtRef cur = seq.ref(t);

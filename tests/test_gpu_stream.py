@@ -67,3 +67,23 @@ def test_stream_launch_back_to_back_shapes():
         wantA, wantB = oracle.cp_mm(P.cpu().numpy(), _host(A), _host(B), primes, rows=rows)
         assert np.array_equal(_host(PA)[:, rows], wantA[:, rows])
         assert np.array_equal(_host(PB)[:, rows], wantB[:, rows])
+
+
+@pytest.mark.parametrize("k", [16384, 16448, 16512, 131071])
+def test_largest_products_closed_form(k):
+    """P = 128, A = 128 and B = q - 128 everywhere: modulo 256 every operand residue is -128, so
+    each INT8 product reaches k 2^14 -- 2^28 at k = 16384, the deepest K whose products the
+    epilogue reduces in single precision; 2^31 - 2^14 at k = 131071, the deepest the form takes.
+    k = 16448 and 16512 run the general reduction with one workgroup per tile (odd K-block count)
+    and in the persistent launch.  Every output is 2^14 k (A part) or -2^14 k (B part) mod q."""
+    print(f"\n[stream] largest products k={k}", flush=True)
+    primes = wl.ntt_primes(50, 1)
+    q = primes[0]
+    m, n = 256, 384
+    P = torch.full((m, k), 128, dtype=torch.int64, device="cuda")
+    A = torch.full((1, k, n), 128, dtype=torch.int64, device="cuda")
+    B = torch.full((1, k, n), q - 128, dtype=torch.int64, device="cuda")
+    PA, PB = hlb.cp_mm(P, A, B, primes, p_absmax=128, form="int8_crt")
+    gA, gB = _host(PA), _host(PB)
+    assert (gA == (k << 14) % q).all()
+    assert (gB == (-(k << 14)) % q).all()
