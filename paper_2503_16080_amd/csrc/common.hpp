@@ -194,6 +194,14 @@ __device__ __forceinline__ void interleave_reads_with_mfmas() {
 // s_waitcnt lgkmcnt(0) that stays after the MFMAs issued before it: an inline-asm wait does
 // not order MFMAs (they touch no memory), so without the scheduling barrier the compiler may
 // hoist it above them and stall on the LDS reads with the matrix pipe idle.
+// Scalar loads share the LDS wait counter but complete out of order, so while the compiler
+// counts one as pending it can wait for an LDS read only with lgkmcnt(0), i.e. for every LDS
+// read in flight.  A wait it can see (not inline assembly) before a K loop settles the scalar
+// loads issued outside it, and the loop's waits then cover only the reads an MFMA needs.
+__device__ __forceinline__ void settle_scalar_loads() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt left at their maxima
+}
+
 __device__ __forceinline__ void wait_lds_after_mfmas() {
     __builtin_amdgcn_sched_barrier(0);
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");

@@ -174,11 +174,15 @@ __device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const in
         const int r = col & (kCrtR - 1);
         return *(const v4i *)(lx + (col / kCrtR) * kCrtSub + r * 64 + ((c ^ swz(r)) << 4));
     };
+    // in the order the MFMAs of a half use them (column block by column block)
     auto read_frags = [&](Frags &f, int buf, int kk) {
+        f.a[0] = frag_a(buf, kk, 0);
+        f.b[0] = frag_b(buf, kk, 0);
+        __builtin_amdgcn_sched_barrier(0);  // the first MFMA's two reads go first
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) f.a[mb] = frag_a(buf, kk, mb);
+        for (int mb = 1; mb < MB; ++mb) f.a[mb] = frag_a(buf, kk, mb);
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) f.b[nb] = frag_b(buf, kk, nb);
+        for (int nb = 1; nb < NB; ++nb) f.b[nb] = frag_b(buf, kk, nb);
     };
     auto mfmas = [&](const Frags &f) {
 #pragma unroll
@@ -249,6 +253,7 @@ __device__ __forceinline__ void crt_tile(int8_t *lds, const int8_t *gP, const in
         };
         const int KBfull = KB - KB % G;
         Frags f;
+        settle_scalar_loads();
 #pragma unroll 1
         for (int kb = 0; kb < KBfull; kb += G) {
             const int b0 = kb % kCrtNbuf, b1 = (kb + 1) % kCrtNbuf;
@@ -400,11 +405,15 @@ __device__ __forceinline__ void crt_tiles(int8_t *lds, int64_t plane_stride, Seq
         const int r = col & (kCrtR - 1);
         return *(const v4i *)(lx + (col / kCrtR) * kCrtSub + r * 64 + ((c ^ swz(r)) << 4));
     };
+    // in the order the MFMAs of a half use them (column block by column block)
     auto read_frags = [&](Frags &f, int buf, int kk) {
+        f.a[0] = frag_a(buf, kk, 0);
+        f.b[0] = frag_b(buf, kk, 0);
+        __builtin_amdgcn_sched_barrier(0);  // the first MFMA's two reads go first
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) f.a[mb] = frag_a(buf, kk, mb);
+        for (int mb = 1; mb < MB; ++mb) f.a[mb] = frag_a(buf, kk, mb);
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) f.b[nb] = frag_b(buf, kk, nb);
+        for (int nb = 1; nb < NB; ++nb) f.b[nb] = frag_b(buf, kk, nb);
     };
 
     // the epilogue of tile r; returns the stores issued
@@ -481,6 +490,7 @@ __device__ __forceinline__ void crt_tiles(int8_t *lds, int64_t plane_stride, Seq
         Src ns = cs;
         zero_acc();
         const int KB = cur.KB;
+        settle_scalar_loads();
         // all groups but the last two: their successors are stages of this tile
 #pragma unroll 1
         for (int kb = 0; kb < KB - 2 * G; kb += G) {
@@ -498,6 +508,7 @@ __device__ __forceinline__ void crt_tiles(int8_t *lds, int64_t plane_stride, Seq
             for (int h = 0; h < G; ++h) gload(cs, kb + h + kCrtNbuf, (ring + kb + h) % kCrtNbuf);
         }
         // the last two groups: the next tile is learnt, and its first stages loaded
+        settle_scalar_loads();
 #pragma unroll 1
         for (int kb = KB - 2 * G; kb < KB; kb += G) {
             const int b0 = (ring + kb) % kCrtNbuf, b1 = (ring + kb + 1) % kCrtNbuf;
@@ -521,6 +532,7 @@ __device__ __forceinline__ void crt_tiles(int8_t *lds, int64_t plane_stride, Seq
                         nxt = seq.ref(tn);
                         ns = source(nxt);
                     }
+                    settle_scalar_loads();
                 }
 #pragma unroll
                 for (int h = 0; h < G; ++h) {
