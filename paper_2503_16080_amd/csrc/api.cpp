@@ -859,6 +859,8 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
         p_tile = f64_plane_bytes_p(1, 1);
         x_tile = f64_plane_bytes_x(pl.nx, 1, 1);
     }
+    // the INT8 tiles address their digit panels with 32-bit byte offsets
+    if (pl.form == HLB_FORM_INT8 && kblocks * std::max(p_tile, x_tile) > (int64_t)UINT32_MAX) return HLB_EINVAL;
     WsLease lease;
     if (pl.form == HLB_FORM_INT8 || planes) {
         const size_t sizes[2] = {(size_t)(tiles_mmax * kblocks * p_tile), (size_t)(tiles_total * kblocks * x_tile)};

@@ -81,6 +81,8 @@ hlb_status build_layout(const hlb_cpmm_problem *probs, int count, const uint64_t
         if (kblocks > lay.kfold) lay.fold = true;
         const int64_t tiles_m = (p.m + pl.bm - 1) / pl.bm;
         const int64_t p_tile = (int64_t)lay.dp * pl.bm * kBK8, x_tile = (int64_t)lay.dx * pl.bn * kBK8;
+        // the tiles address their digit panels with 32-bit byte offsets
+        if (kblocks * std::max(p_tile, x_tile) > (int64_t)UINT32_MAX) return HLB_EINVAL;
 
         BatchProb bp;
         std::memset(&bp, 0, sizeof(bp));

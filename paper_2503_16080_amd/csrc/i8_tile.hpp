@@ -95,11 +95,14 @@ __device__ __forceinline__ void run_tile(const TileJob &job, int8_t *lds) {
         for (int r = 0; r < 16; ++r) part[r] = 0;
     }
 
+    // the buffer form of the direct-to-LDS load: the compiler counts it in vmcnt only, so the
+    // MFMAs wait for just the fragment reads they use (byte offsets within a tile's panels stay
+    // below 2^32: KB P_TILE and KB X_TILE are at most a few hundred MiB)
+    const __amdgpu_buffer_rsrc_t rsP = lds_src_rsrc(job.gP), rsX = lds_src_rsrc(job.gX + T::J0 * T::BN * kBK8);
     auto gload = [&](int kb, int buf) {
         int8_t *dp = lds + buf * T::STAGE;
-        copy_to_lds<T::THREADS, T::P_CHUNKS>(job.gP + (int64_t)kb * T::P_TILE, dp, tid, wave_u);
-        copy_to_lds<T::THREADS, T::X_CHUNKS>(job.gX + (int64_t)kb * T::X_TILE + T::J0 * T::BN * kBK8,
-                                             dp + T::P_TILE, tid, wave_u);
+        copy_to_lds_buf<T::THREADS, T::P_CHUNKS>(rsP, (uint32_t)kb * (uint32_t)T::P_TILE, dp, tid, wave_u);
+        copy_to_lds_buf<T::THREADS, T::X_CHUNKS>(rsX, (uint32_t)kb * (uint32_t)T::X_TILE, dp + T::P_TILE, tid, wave_u);
     };
     const int loads_per_stage = loads_of_wave<T::THREADS, T::P_CHUNKS>(wave_u) +
                                 loads_of_wave<T::THREADS, T::X_CHUNKS>(wave_u);
@@ -164,6 +167,7 @@ __device__ __forceinline__ void run_tile(const TileJob &job, int8_t *lds) {
     wait_vmcnt(outstanding(0, NBUF - 1));
     stage_barrier();
     Frags f0, f1;
+    settle_scalar_loads();
     read_frags(f0, 0, 0);
 #pragma unroll 1
     for (int kb = 0; kb < KB; ++kb) {
