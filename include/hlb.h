@@ -65,8 +65,9 @@ typedef enum {
                               (and m, n >= 256), else INT8 digits, else FP64 */
     HLB_FORM_FP64 = 1,     /* FP64 limbs on v_mfma_f64_16x16x4_f64 */
     HLB_FORM_INT8 = 2,     /* balanced int8 digits on v_mfma_i32_32x32x32_i8 (Strategy 1);
-                              needs k below about 4.7 million (HLB_EINVAL above: the tiles
-                              address their digit panels with 32-bit offsets) */
+                              every k up to 4.79 million runs; deeper K may be refused with
+                              HLB_EINVAL (the tiles address their digit panels with 32-bit
+                              offsets: K blocks x panel bytes per block must stay below 2^32) */
     HLB_FORM_INT8_CRT = 3  /* multimodular: the centred integer product modulo D coprime
                               moduli <= 256, one int8 GEMM each, recombined by the CRT
                               (Strategy 3, FLINT variant); needs k <= 131071 */

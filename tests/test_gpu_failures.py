@@ -73,3 +73,26 @@ def test_eager_batch_workspace_cap(form):
         hlb.set_option(hlb.OPT_BATCH_GRAPH, 1)
     for p, (wA, wB) in zip(probs, want):
         assert np.array_equal(_np(p["PA"]), wA) and np.array_equal(_np(p["PB"]), wB)
+
+
+def test_digit_form_refuses_k_beyond_32_bit_panel_offsets():
+    """The digit tiles address their K panels with 32-bit byte offsets: a K whose panel would
+    pass 2^32 bytes is refused with HLB_EINVAL before anything runs, and the output is left
+    untouched; the multimodular form refuses k > 131071 with HLB_EBOUND."""
+    q = wl.ntt_primes(50, 1)[0]
+    k = 10_000_000
+    print(f"\n[failures] digit form k={k}", flush=True)
+    P = torch.ones((1, k), dtype=torch.int64, device=DEV)
+    X = torch.ones((k, 1), dtype=torch.int64, device=DEV)
+    C = torch.full((1, 1), -1, dtype=torch.int64, device=DEV)
+    with pytest.raises(hlb.HlbError) as err:
+        hlb.mod_pp_mm(q, P, X, form="int8", out=C)
+    assert err.value.status == 1  # HLB_EINVAL
+    with pytest.raises(hlb.HlbError) as err:
+        hlb.mod_pp_mm(q, P, X, form="int8_crt", out=C)
+    assert err.value.status == 3  # HLB_EBOUND
+    assert int(C[0, 0]) == -1
+    # a K just inside the digit bound still runs (ones: the product is k mod q)
+    k2 = 1 << 20
+    got = hlb.mod_pp_mm(q, P[:, :k2].contiguous(), X[:k2].contiguous(), form="int8")
+    assert int(_np(got)[0, 0]) == k2 % q
