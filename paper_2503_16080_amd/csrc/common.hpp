@@ -110,7 +110,9 @@ __device__ __forceinline__ void copy_to_lds(const int8_t *src, int8_t *dst, int 
 
 // The same copy with the buffer form of the direct-to-LDS load (MUBUF ... lds): the source
 // is `rsrc` + src_off, byte offsets below 2^32.  The compiler counts these loads in vmcnt only,
-// so LDS fragment reads after them can wait for just the reads they need.
+// so LDS fragment reads after them can wait for just the reads they need.  src_off is
+// wave-uniform and goes in the scalar offset; the per-lane offset is the same for every
+// stage and block, so one register serves all loads.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t lds_src_rsrc(const int8_t *base) {
     // the base is wave-uniform; say so, so that the descriptor lives in scalar registers
     const uint64_t p = (uint64_t)(uintptr_t)base;
@@ -127,7 +129,8 @@ __device__ __forceinline__ void copy_to_lds_buf(__amdgpu_buffer_rsrc_t rsrc, uin
         const int base = i * THREADS + wave_u * 64;  // wave-uniform
         if (CHUNKS % THREADS == 0 || base < CHUNKS)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)(dst + base * 16),
-                                                     16, src_off + (uint32_t)(i * THREADS + tid) * 16u, 0, 0, 0);
+                                                     16, (uint32_t)(i * THREADS + tid) * 16u,
+                                                     __builtin_amdgcn_readfirstlane(src_off), 0, 0);
     }
 }
 
