@@ -53,6 +53,12 @@ def _parse():
     ap.add_argument("--no-extra-configs", action="store_true",
                     help="skip the legs of the other workloads: d = 4096 FP64 form, d = 16384 over 2 "
                          "primes, and the 64-problem batch")
+    ap.add_argument("--config", type=int, choices=[1, 2, 3, 4, 5],
+                    help="one configuration alone, as its own JSON line: 1 a single Mod-PP-MM "
+                         "256^3 over one 50-bit prime, FP64-limb form; 2 CP-MM d = 4096 over 3 "
+                         "primes, FP64-limb form; 3 the headline (d = 8192 over 3 primes, INT8 "
+                         "forms beside the FP64 form); 4 the 64-problem batch; 5 CP-MM d = 16384 "
+                         "over 2 primes, multimodular INT8 form")
     ap.add_argument("--workload", choices=["cpmm", "batch", "trunc"], default="cpmm",
                     help="cpmm: one CP-MM of size --d (default); batch: 64 CP-MMs of uneven "
                          "shapes over 4 primes of 45 bits; trunc: the CP-MM of size --d with "
@@ -462,6 +468,73 @@ def config2_leg(steps, warmup):
     return out
 
 
+def config1_leg(steps, warmup, cpu=True):
+    """One Mod-PP-MM_{q; 256,256,256} (Section 5 notation), P and X uniform in [0, q) for one
+    50-bit NTT-friendly prime, in the plain FP64-limb form; the oracle computes the same
+    product on the host cores."""
+    import numpy as np
+    import torch
+
+    import paper_2503_16080_amd as hlb
+    import workloads as wl
+
+    n = 256
+    q = wl.ntt_primes(50, 1)[0]
+    g = wl.rng(1001)
+    P = g.integers(0, q, size=(n, n), dtype=np.uint64)
+    X = g.integers(0, q, size=(n, n), dtype=np.uint64)
+    Pd = torch.from_numpy(P.view(np.int64)).cuda()
+    Xd = torch.from_numpy(X.view(np.int64)).cuda()
+    C = torch.empty((n, n), dtype=torch.int64, device=Pd.device)
+    s, kf = _profiled(lambda: hlb.mod_pp_mm(q, Pd, Xd, form="fp64", out=C), ("gemm_f64",), steps, warmup)
+    plan = hlb.plan(0, n, q, 1, "fp64")
+    macs = n ** 3
+    launches, ms = kf["gemm_f64"]
+    f_ops = 2.0 * plan["p_limbs"] * plan["x_limbs"] * macs / max(launches / steps, 1e-9)
+    rate = f_ops / (ms * 1e-3) / 1e12
+    out = {"value": macs / s, "unit": "mod-q MAC/s", "ms_per_step": s * 1e3,
+           "workload": f"mod_pp_mm q of 50 bits, {n}x{n} times {n}x{n} residues, FP64-limb form "
+                       f"({plan['p_limbs']} x {plan['x_limbs']} limbs of {plan['limb_bits']} bits)",
+           "roofline": {"bound": "mfma", "achieved": rate, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": rate / FP64_PEAK_TFLOPS, "traffic": None, "traffic_gbs": None,
+                        "kernel": "gemm_f64_kernel", "avg_launch_ms": ms, "launches": launches,
+                        "launches_per_step": launches / steps, "ops_per_launch": f_ops, "op": "fp64 MAC x 2",
+                        "note": "one 256^3 product: too few output tiles to fill 256 CUs"}}
+    if cpu:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.mod_pp_mm(q, P, X)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": macs / dt, "unit": "mod-q MAC/s", "cores": oracle.num_threads(),
+                               "cpu_model": cpu_model(), "kind": "oracle",
+                               "sample": f"the whole {n}^3 product, {dt:.3f} s"}
+    del Pd, Xd, C
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_config(args):
+    """--config N: one configuration alone, as its own JSON line."""
+    c = args.config
+    steps, warmup = args.steps, args.warmup
+    line = {"n_gpus": 1, "steps": steps, "warmup": warmup, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "data": "synthetic"}
+    if c == 1:
+        res = config1_leg(steps, warmup, cpu=not args.no_cpu_baseline)
+        metric, dtype = "Mod-PP-MM mod-q MACs/s, 256^3, one 50-bit prime, FP64-limb form", "f64"
+    elif c == 2:
+        res = config2_leg(steps, warmup)
+        metric, dtype = "CP-MM mod-q MACs/s at d=4096, FP64-limb form; ratio to FP64 GEMM", "f64"
+    else:
+        res = config5_leg(steps, warmup)
+        metric, dtype = "CP-MM mod-q MACs/s at d=16384, INT8-limb form; ratio to FP64 GEMM", "i8"
+    line.update({"metric": metric, "value": res.pop("value"), "unit": res.pop("unit"),
+                 "ms_per_step": res.pop("ms_per_step"), "dtype": dtype,
+                 "config": {"workload": res.pop("workload"), "config": c}})
+    line.update(res)
+    print(json.dumps(line), flush=True)
+
+
 def config5_leg(steps, warmup):
     """CP-MM at d = 16384 over 2 primes of 50 bits (2 GiB per residue matrix) in the
     multimodular INT8 form, inputs drawn on the device, against the same-shape vendor dgemm."""
@@ -635,7 +708,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    if args.workload == "batch":
+    if args.config in (1, 2, 5):
+        run_config(args)
+        return
+    if args.config == 3:
+        args.no_extra_configs = True
+    if args.workload == "batch" or args.config == 4:
         run_batch(args)
         return
     if args.workload == "trunc":

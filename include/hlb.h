@@ -283,12 +283,30 @@ typedef enum {
                                  2 = 256 x 384 outputs, 1 = 256 x 256, 0 = 256 x 128 force a
                                  class for every call and batch problem; other values are
                                  refused with HLB_EINVAL.  Results are identical. */
-    HLB_OPT_WS_CAP = 7        /* > 0: refuse any single stream-ordered workspace allocation
+    HLB_OPT_WS_CAP = 7,       /* > 0: refuse any single stream-ordered workspace allocation
                                  above this many bytes with HLB_ENOMEM, before any launch
                                  that would use it (a host-side way to exercise the
                                  out-of-memory paths); 0 (default): no cap.  Cached batch
                                  graphs allocate their own workspace and are not capped. */
+    HLB_OPT_VALIDATE = 8      /* 1: hlb_mod_pp_mm, hlb_cp_mm and hlb_cp_mm_batch first check
+                                 their inputs on the device -- every residue below its
+                                 modulus (hlb_validate_residues), every |P| within p_absmax
+                                 when one is given (hlb_plaintext_absmax) -- and return
+                                 HLB_ERANGE before writing any output if one is not.  The
+                                 checks synchronise the stream, so a capturing stream gets
+                                 HLB_EINVAL.  hlb_cp_mm_noalloc and hlb_ccmm_pp_core do not
+                                 check.  0 (default): no checks.  Starts at 1 when the
+                                 environment holds HLB_VALIDATE=1. */
 } hlb_option;
+
+/*
+ * Environment, read once per process:
+ *   HLB_FORM=auto|fp64|int8|int8_crt  the form of every call that passes HLB_FORM_AUTO
+ *                                      (hlb_plan included); explicit forms are kept.
+ *   HLB_VALIDATE=1                     starts HLB_OPT_VALIDATE on.
+ *   HLB_TUNE_CACHE=path                tuning table loaded before the first lookup
+ *                                      (hlb_tune_load's format).
+ */
 
 hlb_status hlb_set_option(int option, int64_t value);
 

@@ -34,6 +34,7 @@ FORM_AUTO, FORM_FP64, FORM_INT8, FORM_INT8_CRT = 0, 1, 2, 3
 _FORMS = {"auto": FORM_AUTO, "fp64": FORM_FP64, "int8": FORM_INT8, "int8_crt": FORM_INT8_CRT}
 OPT_FORCE_KCHUNK, OPT_PROFILE, OPT_BATCH_GRAPH, OPT_FORCE_CLASS, OPT_F64_PLANES, OPT_CRT_WIDE = 1, 2, 3, 4, 5, 6
 OPT_WS_CAP = 7
+OPT_VALIDATE = 8
 NOALLOC_SCRATCH_BYTES = 256 << 20   # HLB_NOALLOC_SCRATCH_BYTES
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

@@ -34,6 +34,30 @@ static std::atomic<int> g_f64_planes{1};
 static std::atomic<int> g_crt_wide{-1};  // -1: the tuned class per shape
 static std::atomic<int64_t> g_ws_cap{0};
 
+// Environment switches, read once per process: HLB_FORM names the form of calls that pass
+// HLB_FORM_AUTO (auto, fp64, int8 or int8_crt); HLB_VALIDATE=1 starts HLB_OPT_VALIDATE on.
+static std::once_flag g_env_once;
+static std::atomic<int> g_env_form{HLB_FORM_AUTO};
+static std::atomic<int> g_validate{0};
+static void read_env() {
+    std::call_once(g_env_once, [] {
+        if (const char *f = std::getenv("HLB_FORM")) {
+            if (!std::strcmp(f, "fp64")) g_env_form.store(HLB_FORM_FP64);
+            else if (!std::strcmp(f, "int8")) g_env_form.store(HLB_FORM_INT8);
+            else if (!std::strcmp(f, "int8_crt")) g_env_form.store(HLB_FORM_INT8_CRT);
+        }
+        if (const char *v = std::getenv("HLB_VALIDATE")) g_validate.store(*v && std::strcmp(v, "0") ? 1 : 0);
+    });
+}
+int resolve_form(int form) {
+    read_env();
+    return form == HLB_FORM_AUTO ? g_env_form.load() : form;
+}
+bool opt_validate() {
+    read_env();
+    return g_validate.load() != 0;
+}
+
 int64_t opt_force_kchunk() { return g_force_kchunk.load(); }
 bool opt_batch_graph() { return g_batch_graph.load() != 0; }
 
@@ -1027,6 +1051,7 @@ hlb_status cp_mm_entry(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64
     hlb_status st = cp_mm_prepare(m, k, nA, nB, P, ldp, &p_absmax, A, B, primes, L, PA, PB, s, &qmin, &qmax,
                                   &n_xcd, &nothing);
     if (st != HLB_OK || nothing) return st;
+    form = resolve_form(form);
     Plan pl;
     if ((st = plan(1, k, qmax, std::max<int64_t>(p_absmax, 1), form, &pl)) != HLB_OK) return st;
     auto_for_shape(&pl, form, m, std::max(nA, nB), k, qmax, std::max<int64_t>(p_absmax, 1));
@@ -1046,6 +1071,31 @@ hlb_status cp_mm_entry(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64
         }
     }
     return run_products(pl, {left}, rights, k, n_xcd, s);
+}
+
+// The input checks of HLB_OPT_VALIDATE for one CP-MM (synchronous; HLB_EINVAL on a capturing
+// stream): every residue of A and B below its prime, every |P| within p_absmax (when one is
+// given).  HLB_ERANGE on the first violation; arguments the call itself refuses pass here.
+hlb_status validate_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp,
+                          int64_t p_absmax, const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L,
+                          void *stream) {
+    if (m <= 0 || k <= 0 || L <= 0 || L > 1024 || !primes || (nA <= 0 && nB <= 0) || !P || ldp < k) return HLB_OK;
+    if ((nA > 0 && !A) || (nB > 0 && !B)) return HLB_OK;
+    int64_t bad = -1;
+    for (int l = 0; l < L; ++l) {
+        if (check_modulus(primes[l]) != HLB_OK) return HLB_OK;
+        hlb_status v = HLB_OK;
+        if (nA > 0) v = hlb_validate_residues(A + (int64_t)l * k * nA, k, nA, nA, primes[l], &bad, stream);
+        if (v == HLB_OK && nB > 0) v = hlb_validate_residues(B + (int64_t)l * k * nB, k, nB, nB, primes[l], &bad, stream);
+        if (v != HLB_OK) return v;
+    }
+    if (p_absmax > 0) {
+        int64_t mx = 0;
+        const hlb_status v = hlb_plaintext_absmax(P, m, k, ldp, &mx, stream);
+        if (v != HLB_OK) return v;
+        if (mx > p_absmax) return HLB_ERANGE;
+    }
+    return HLB_OK;
 }
 
 }  // namespace hlb
@@ -1075,7 +1125,7 @@ hlb_status hlb_plan(int kind, int64_t k, uint64_t q_max, int64_t p_absmax, int f
     if (!out || (kind != 0 && kind != 1) || k < 0 || check_modulus(q_max) != HLB_OK) return HLB_EINVAL;
     if (kind == 1 && (p_absmax < 1 || (uint64_t)p_absmax >= kMaxModulus)) return HLB_EINVAL;
     Plan pl;
-    const hlb_status st = plan(kind, k, q_max, p_absmax, form, &pl);
+    const hlb_status st = plan(kind, k, q_max, p_absmax, resolve_form(form), &pl);
     if (st != HLB_OK) return st;
     out->form = pl.form;
     out->p_limbs = pl.np;
@@ -1093,6 +1143,13 @@ hlb_status hlb_mod_pp_mm(uint64_t q, int64_t m, int64_t k, int64_t n, const uint
     if (check_modulus(q) != HLB_OK || m < 0 || k < 0 || n < 0) return HLB_EINVAL;
     if (m == 0 || n == 0) return HLB_OK;
     if (!C || ldc < n || (k > 0 && (!P || !X || ldp < k || ldx < n))) return HLB_EINVAL;
+    form = resolve_form(form);
+    if (opt_validate() && k > 0) {
+        int64_t bad = -1;
+        hlb_status v = hlb_validate_residues(P, m, k, ldp, q, &bad, stream);
+        if (v == HLB_OK) v = hlb_validate_residues(X, k, n, ldx, q, &bad, stream);
+        if (v != HLB_OK) return v;
+    }
     Plan pl;
     hlb_status st = plan(0, k, q, 0, form, &pl);
     if (st != HLB_OK) return st;
@@ -1108,6 +1165,10 @@ hlb_status hlb_mod_pp_mm(uint64_t q, int64_t m, int64_t k, int64_t n, const uint
 hlb_status hlb_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp,
                      int64_t p_absmax, const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L,
                      uint64_t *PA, uint64_t *PB, int form, void *stream) {
+    if (opt_validate()) {
+        const hlb_status v = validate_cp_mm(m, k, nA, nB, P, ldp, p_absmax, A, B, primes, L, stream);
+        if (v != HLB_OK) return v;
+    }
     return cp_mm_entry(m, k, nA, nB, P, ldp, p_absmax, A, B, primes, L, PA, PB, form, (hipStream_t)stream);
 }
 
@@ -1191,6 +1252,7 @@ hlb_status hlb_ccmm_pp_core(int64_t m, int64_t k, int64_t n, const uint64_t *A, 
         if (check_modulus(primes[l]) != HLB_OK) return HLB_EINVAL;
         qmax = std::max(qmax, primes[l]);
     }
+    form = resolve_form(form);
     Plan pl;
     hlb_status st = plan(0, k, qmax, 0, form, &pl);
     if (st != HLB_OK) return st;
@@ -1310,6 +1372,10 @@ hlb_status hlb_set_option(int option, int64_t value) {
         case HLB_OPT_WS_CAP:
             if (value < 0) return HLB_EINVAL;
             g_ws_cap.store(value);
+            return HLB_OK;
+        case HLB_OPT_VALIDATE:
+            read_env();  // the option set here outlasts the environment's value
+            g_validate.store(value ? 1 : 0);
             return HLB_OK;
         default: return HLB_EUNSUP;
     }

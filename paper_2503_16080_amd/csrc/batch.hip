@@ -712,6 +712,14 @@ extern "C" hlb_status hlb_cp_mm_batch(const hlb_cpmm_problem *probs, int count, 
     hipStream_t s = (hipStream_t)stream;
     hlb_status st = device_ready(nullptr);
     if (st != HLB_OK) return st;
+    form = resolve_form(form);
+    if (opt_validate()) {
+        for (int i = 0; i < count; ++i) {
+            const hlb_cpmm_problem &p = probs[i];
+            st = validate_cp_mm(p.m, p.k, p.nA, p.nB, p.P, p.ldp, p.p_absmax, p.A, p.B, primes, L, stream);
+            if (st != HLB_OK) return st;
+        }
+    }
 
     // The persistent INT8 path needs every plaintext within 3 digits; other batches (and the
     // FP64 form) run problem by problem through hlb_cp_mm.

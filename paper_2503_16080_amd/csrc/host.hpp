@@ -109,6 +109,14 @@ class ScratchScope {
 hlb_status cp_mm_entry(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp, int64_t p_absmax,
                        const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L, uint64_t *PA, uint64_t *PB,
                        int form, hipStream_t s);
+// HLB_OPT_VALIDATE's checks of one CP-MM's inputs (synchronous; HLB_ERANGE on a violation).
+hlb_status validate_cp_mm(int64_t m, int64_t k, int64_t nA, int64_t nB, const int64_t *P, int64_t ldp,
+                          int64_t p_absmax, const uint64_t *A, const uint64_t *B, const uint64_t *primes, int L,
+                          void *stream);
+// The form a call runs: `form`, or the HLB_FORM environment's form where `form` is
+// HLB_FORM_AUTO.
+int resolve_form(int form);
+bool opt_validate();
 int64_t opt_force_kchunk();
 bool opt_batch_graph();
 void batch_release();

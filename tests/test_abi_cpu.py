@@ -339,3 +339,35 @@ def test_binding_rejects_mismatched_tensors_before_device_work():
         hlb.cp_mm(c(m, k), c(L, k, n), c(L, k, n), q, out=(c(L, m, n), c(L, m, n)))
     with pytest.raises(TypeError):
         hlb.cp_mm_batch([dict(P=c(m, k), A=c(L, k, n), B=c(L, k, n))], q)
+
+
+def test_environment_form_switch_and_validate_option():
+    """HLB_FORM sets the form of calls that pass HLB_FORM_AUTO (hlb_plan included) and leaves
+    explicit forms alone; HLB_OPT_VALIDATE is a host-side option (accepted without a GPU).  The
+    environment is read once per process, so each setting runs in a fresh interpreter."""
+    import json
+    import subprocess
+    import sys
+    q = wl.ntt_primes(50, 1)[0]
+    code = ("import json, paper_2503_16080_amd as h; "
+            f"print(json.dumps([h.plan(1, 8192, {q}, 1 << 20, 'auto')['form'], "
+            f"h.plan(1, 8192, {q}, 1 << 20, 'int8')['form']]))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    got = {}
+    for env_form in (None, "fp64", "int8", "int8_crt", "auto", "bogus"):
+        env = dict(os.environ)
+        env.pop("HLB_FORM", None)
+        if env_form is not None:
+            env["HLB_FORM"] = env_form
+        r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 0, r.stderr
+        got[env_form] = json.loads(r.stdout.strip().splitlines()[-1])
+    # auto picks the multimodular form at d = 8192; an unknown name is ignored
+    assert got[None] == [hlb.FORM_INT8_CRT, hlb.FORM_INT8]
+    assert got["fp64"] == [hlb.FORM_FP64, hlb.FORM_INT8]
+    assert got["int8"] == [hlb.FORM_INT8, hlb.FORM_INT8]
+    assert got["int8_crt"] == [hlb.FORM_INT8_CRT, hlb.FORM_INT8]
+    assert got["auto"] == got[None] and got["bogus"] == got[None]
+    hlb.set_option(hlb.OPT_VALIDATE, 1)
+    hlb.set_option(hlb.OPT_VALIDATE, 0)
