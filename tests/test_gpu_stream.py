@@ -87,3 +87,42 @@ def test_largest_products_closed_form(k):
     gA, gB = _host(PA), _host(PB)
     assert (gA == (k << 14) % q).all()
     assert (gB == (-(k << 14)) % q).all()
+
+
+@pytest.mark.parametrize("k", [16448, 20096])
+def test_general_reduction_random_deep_k(k):
+    """Random operands past 256 K blocks, where the epilogue takes the general twelve-operation
+    reduction: 257 blocks (odd: one workgroup per tile) and 314 (even: the persistent launch).
+    Sampled rows against the oracle and every entry against the digit form."""
+    print(f"\n[stream] general reduction k={k}", flush=True)
+    m, n, L = 300, 400, 2
+    primes, P, A, B = wl.cpmm_uniform_device(7300 + k, m, k, n, 50, L)
+    PA, PB = hlb.cp_mm(P, A, B, primes, p_absmax=1 << 20, form="int8_crt")
+    DA, DB = hlb.cp_mm(P, A, B, primes, p_absmax=1 << 20, form="int8")
+    torch.cuda.synchronize()
+    assert torch.equal(PA, DA) and torch.equal(PB, DB)
+    rows = [0, 255, 256, m - 1]
+    wantA, wantB = oracle.cp_mm(P.cpu().numpy(), _host(A), _host(B), primes, rows=rows)
+    assert np.array_equal(_host(PA)[:, rows], wantA[:, rows])
+    assert np.array_equal(_host(PB)[:, rows], wantB[:, rows])
+
+
+def test_seeded_sweep_of_small_shapes():
+    """Forty seeded shapes (m, k, n from 1 to 700, 1 to 4 primes, plaintext bounds from 1 to
+    2^40): each against the oracle in full."""
+    g = np.random.default_rng(7400)
+    for i in range(40):
+        m, k, n = (int(x) for x in g.integers(1, 700, size=3))
+        L = int(g.integers(1, 5))
+        pbits = int(g.integers(0, 41))
+        print(f"\n[stream] sweep {i}: m={m} k={k} n={n} L={L} pbits={pbits}", flush=True)
+        primes = wl.ntt_primes(int(g.integers(30, 53)), L, skip=i % 8)
+        pmax = 1 << pbits
+        P = g.integers(-pmax, pmax + 1, size=(m, k), dtype=np.int64)
+        A = np.stack([g.integers(0, q, size=(k, n), dtype=np.uint64) for q in primes])
+        B = np.stack([g.integers(0, q, size=(k, n), dtype=np.uint64) for q in primes])
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
+        PA, PB = hlb.cp_mm(t(P), t(A), t(B), primes, p_absmax=pmax, form="int8_crt")
+        wantA, wantB = oracle.cp_mm(P, A, B, primes)
+        assert np.array_equal(_host(PA), wantA), i
+        assert np.array_equal(_host(PB), wantB), i
