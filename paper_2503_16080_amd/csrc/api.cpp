@@ -622,7 +622,13 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
     int cus = 256;
     (void)device_ready(nullptr, &cus);
     const int64_t bn = crt_tile_cols(wide), xsub = bn / 128;
-    const int64_t kblocks = (k + kBK8 - 1) / kBK8;
+    // The persistent launch of the 256 x 384 tiles takes even K-block counts only: an odd count
+    // of at least kCrtPadOddKB gets one more block, all zeros (the splits write zeros past k),
+    // which costs less than the per-tile launch it avoids (measured: the persistent launch saves
+    // 2-3 us per tile, 2-10 % of a tile at these depths; the block adds 1/KB of the work).
+    constexpr int64_t kCrtPadOddKB = 15;
+    int64_t kblocks = (k + kBK8 - 1) / kBK8;
+    if (wide == 2 && kblocks % 2 == 1 && kblocks >= kCrtPadOddKB) ++kblocks;
     const int64_t sub = (int64_t)D * 128 * kBK8;  // bytes of one 128-wide tile and k block
     int64_t mmax = 0;
     for (const LeftSpec &L : lefts) mmax = std::max(mmax, L.m);

@@ -1,7 +1,8 @@
 """GPU parity of the multimodular GEMM's persistent launch, where each workgroup runs many
 tiles as one stream of pipeline stages and takes them from per-XCD queues (tile counts far
 above the CU count, K-block counts of 4 -- the shortest tile the stream takes -- 6 and 32,
-ragged m and n), and of the one-tile-per-workgroup launch it falls back to (odd or short K).
+ragged m and n, and an odd count of 17 padded with a zero block to 18), and of the
+one-tile-per-workgroup launch it falls back to (K-block counts odd and below 15, or below 4).
 
 Every output matrix is checked against the oracle by Freivalds' test (P (X r) = C r mod q for
 random r) and on sampled rows element by element; the products are also compared element by
@@ -27,7 +28,8 @@ def _host(t):
     (2048, 256, 2048, 3),   # 4 K blocks: 2816 tiles, the next tile learnt at the first group
     (1000, 384, 1500, 2),   # 6 K blocks, ragged rows and columns
     (777, 2000, 3000, 3),   # 32 K blocks (the last one partial)
-    (1500, 1088, 1000, 2),  # 17 K blocks: odd, one workgroup per tile
+    (1500, 1088, 1000, 2),  # 17 K blocks: odd, padded with a zero block to 18
+    (1500, 576, 1000, 2),   # 9 K blocks: odd and short, one workgroup per tile
     (1500, 128, 1000, 2),   # 2 K blocks: shorter than the ring, one workgroup per tile
 ])
 def test_stream_launch_vs_oracle_and_digit_form(m, k, n, L):
@@ -69,35 +71,45 @@ def test_stream_launch_back_to_back_shapes():
         assert np.array_equal(_host(PB)[:, rows], wantB[:, rows])
 
 
-@pytest.mark.parametrize("k", [16384, 16448, 16512, 131071])
-def test_largest_products_closed_form(k):
+@pytest.mark.parametrize("k,cls", [(16384, -1), (16448, -1), (16448, 1), (16512, -1), (131071, -1)])
+def test_largest_products_closed_form(k, cls):
     """P = 128, A = 128 and B = q - 128 everywhere: modulo 256 every operand residue is -128, so
     each INT8 product reaches k 2^14 -- 2^28 at k = 16384, the deepest K whose products the
     epilogue reduces in single precision; 2^31 - 2^14 at k = 131071, the deepest the form takes.
-    k = 16448 and 16512 run the general reduction with one workgroup per tile (odd K-block count)
-    and in the persistent launch.  Every output is 2^14 k (A part) or -2^14 k (B part) mod q."""
-    print(f"\n[stream] largest products k={k}", flush=True)
+    k = 16448 (257 K blocks, padded to 258) and 16512 run the general reduction in the
+    persistent launch, and with the 256 x 256 tiles forced, one workgroup per tile.  Every
+    output is 2^14 k (A part) or -2^14 k (B part) mod q."""
+    print(f"\n[stream] largest products k={k} class={cls}", flush=True)
     primes = wl.ntt_primes(50, 1)
     q = primes[0]
     m, n = 256, 384
     P = torch.full((m, k), 128, dtype=torch.int64, device="cuda")
     A = torch.full((1, k, n), 128, dtype=torch.int64, device="cuda")
     B = torch.full((1, k, n), q - 128, dtype=torch.int64, device="cuda")
-    PA, PB = hlb.cp_mm(P, A, B, primes, p_absmax=128, form="int8_crt")
+    try:
+        hlb.set_option(hlb.OPT_CRT_WIDE, cls)
+        PA, PB = hlb.cp_mm(P, A, B, primes, p_absmax=128, form="int8_crt")
+    finally:
+        hlb.set_option(hlb.OPT_CRT_WIDE, -1)
     gA, gB = _host(PA), _host(PB)
     assert (gA == (k << 14) % q).all()
     assert (gB == (-(k << 14)) % q).all()
 
 
-@pytest.mark.parametrize("k", [16448, 20096])
-def test_general_reduction_random_deep_k(k):
+@pytest.mark.parametrize("k,cls", [(16448, -1), (16448, 1), (20096, -1)])
+def test_general_reduction_random_deep_k(k, cls):
     """Random operands past 256 K blocks, where the epilogue takes the general twelve-operation
-    reduction: 257 blocks (odd: one workgroup per tile) and 314 (even: the persistent launch).
-    Sampled rows against the oracle and every entry against the digit form."""
-    print(f"\n[stream] general reduction k={k}", flush=True)
+    reduction: 257 blocks (padded to 258) and 314 in the persistent launch, and 257 with the
+    256 x 256 tiles forced (one workgroup per tile).  Sampled rows against the oracle and every
+    entry against the digit form."""
+    print(f"\n[stream] general reduction k={k} class={cls}", flush=True)
     m, n, L = 300, 400, 2
     primes, P, A, B = wl.cpmm_uniform_device(7300 + k, m, k, n, 50, L)
-    PA, PB = hlb.cp_mm(P, A, B, primes, p_absmax=1 << 20, form="int8_crt")
+    try:
+        hlb.set_option(hlb.OPT_CRT_WIDE, cls)
+        PA, PB = hlb.cp_mm(P, A, B, primes, p_absmax=1 << 20, form="int8_crt")
+    finally:
+        hlb.set_option(hlb.OPT_CRT_WIDE, -1)
     DA, DB = hlb.cp_mm(P, A, B, primes, p_absmax=1 << 20, form="int8")
     torch.cuda.synchronize()
     assert torch.equal(PA, DA) and torch.equal(PB, DB)
