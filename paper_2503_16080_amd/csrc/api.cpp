@@ -322,8 +322,8 @@ hlb_status plan(int kind, int64_t k, uint64_t qmax, int64_t pmax, int form, Plan
     if (form == HLB_FORM_INT8_CRT) return plan_crt(kind, k, qmax, pmax, pl);
     if (form == HLB_FORM_AUTO) {
         // the multimodular form when its D int8 products clearly undercut the digit pairs
-        // (both measured at d = 8192: 11 moduli at 48-50 % of the int8 peak beat 21 digit
-        // pairs at 50 %, 1.7x faster per CP-MM); the digit form otherwise, FP64 where no int8
+        // (both measured at d = 8192: 11 moduli at 50-51 % of the int8 peak beat 21 digit
+        // pairs at 49 %, 1.8x faster per CP-MM); the digit form otherwise, FP64 where no int8
         // plan exists
         Plan digit, crt;
         digit.kind = crt.kind = kind;
