@@ -5,9 +5,10 @@ benchmark times:
   multimodular and digit INT8 forms;
 * the batch: 64 CP-MMs of uneven shapes (m, d log-uniform, n = d) over 4 primes of 45 bits,
   one batch call in each batch form (Theorem th:pcmm-shs applied to every problem);
-* the end-to-end CKKS check at d = 4096 over 3 primes in the multimodular form: a real
-  encryption (Eq mat_row_format), the product, decryption (Section 2.2 Dec), the CRT lift and
-  decoding, within the noise bound.
+* the end-to-end CKKS check in the multimodular form at d = 4096 and at the headline size
+  d = 8192 over 3 primes, and at d = 16384 over 2 primes: a real encryption (Eq
+  mat_row_format), the product, decryption (Section 2.2 Dec), the CRT lift and decoding,
+  within the noise bound.
 
 Every output matrix is checked by Freivalds' test against the oracle (P (X r) = C r mod q for
 random r; a wrong matrix passes one vector with probability <= 1/q), and sampled rows (first,
@@ -133,10 +134,10 @@ def test_batch_64_uneven_problems(batch64, form):
 # End to end at d = 4096 over 3 primes, multimodular form
 # ------------------------------------------------------------------------------------------
 
-def test_ckks_end_to_end_d4096_multimodular():
-    d, L = 4096, 3
+@pytest.mark.parametrize("d,L,seed", [(4096, 3, 1002), (8192, 3, 1003), (16384, 2, 1005)])
+def test_ckks_end_to_end_multimodular(d, L, seed):
     print(f"\n[configs] CKKS end to end d={d} L={L} int8_crt", flush=True)
-    dr = wl.ckks_draws(seed=1002, m=d, k=d, n=d, bits=50, L=L)
+    dr = wl.ckks_draws(seed=seed, m=d, k=d, n=d, bits=50, L=L)
     primes = dr.primes
     delta = 2.0 ** dr.delta_bits
     ME = oracle.encode(dr.M, delta) + dr.E                 # the encoded message plus error
@@ -145,7 +146,7 @@ def test_ckks_end_to_end_d4096_multimodular():
     gS = torch.from_numpy(dr.S).to(DEV)
     gB = hlb.hlb_test_encrypt(gA, gS, torch.from_numpy(ME).to(DEV), primes)
     B = _host(gB)
-    g = np.random.default_rng(4096)
+    g = np.random.default_rng(d)
     # the ciphertext is a valid encryption: A S + B = encode(M) + E (mod q_i), by Freivalds
     for i, q in enumerate(primes):
         Sq = oracle.residues_of_signed(dr.S, q)
@@ -159,13 +160,13 @@ def test_ckks_end_to_end_d4096_multimodular():
     PA, PB = _host(gPA), _host(gPB)
     del gPA, gPB, gA, gB, gS, gP
     rows = _rows(d)
-    _Expect(P, dr.A, B, primes, rows, vectors=2, seed=4097).verify(PA, PB, "ckks cp_mm")
+    _Expect(P, dr.A, B, primes, rows, vectors=2, seed=d + 1).verify(PA, PB, "ckks cp_mm")
     # decryption of the sampled rows: (P A) S + P B = P (encode(M) + E) (mod q_i), exactly
     D = oracle.decrypt(PA[:, rows], PB[:, rows], dr.S, primes)
     for i, q in enumerate(primes):
         want = oracle.mod_pp_mm(q, oracle.residues_of_signed(P[rows], q), oracle.residues_of_signed(ME, q))
         assert np.array_equal(D[i], want), (i, "decryption congruence")
-    # the CRT lift is the exact integer product P (encode(M) + E) (|.| < 2^73 < Q / 2): formed
+    # the CRT lift is the exact integer product P (encode(M) + E) (|.| < 2^74 < Q / 2): formed
     # here from two exact int64 products over 20-bit halves of encode(M) + E
     lifted = oracle.crt_lift_centered(D, primes)
     lo = ME & ((1 << 20) - 1)
