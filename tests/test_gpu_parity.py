@@ -225,3 +225,32 @@ def test_determinism():
     ref = (_np(outs[0][0]), _np(outs[0][1]))
     for PA, PB in outs[1:]:
         assert np.array_equal(_np(PA), ref[0]) and np.array_equal(_np(PB), ref[1])
+
+
+def test_determinism_across_runs_tile_classes_and_forms():
+    """Bytes identical over repeated calls (the persistent multimodular launch takes its tiles
+    from atomic queues, in an order that changes from run to run), over every tile class of
+    both INT8 forms, and across the three forms.  1024 x 512 x 1536 over 3 primes: 528
+    multimodular tiles of 256 x 384, more than one per CU."""
+    w = wl.cpmm_uniform(72, 1024, 512, 1536, 50, 3)
+    P, A, B = _t(w.P), _t(w.A), _t(w.B)
+    outs = []
+    try:
+        for cls in (2, 2, 2, 1, 0):
+            hlb.set_option(hlb.OPT_CRT_WIDE, cls)
+            outs.append(hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form="int8_crt"))
+        hlb.set_option(hlb.OPT_CRT_WIDE, -1)
+        for cls in (0, 1):
+            hlb.set_option(hlb.OPT_FORCE_CLASS, cls)
+            outs.append(hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form="int8"))
+        hlb.set_option(hlb.OPT_FORCE_CLASS, -1)
+        outs.append(hlb.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form="fp64"))
+    finally:
+        hlb.set_option(hlb.OPT_CRT_WIDE, -1)
+        hlb.set_option(hlb.OPT_FORCE_CLASS, -1)
+    ref = (_np(outs[0][0]), _np(outs[0][1]))
+    for i, (PA, PB) in enumerate(outs[1:]):
+        assert np.array_equal(_np(PA), ref[0]) and np.array_equal(_np(PB), ref[1]), i
+    rows = [0, 255, 256, 1023]
+    wantA, wantB = oracle.cp_mm(w.P, w.A, w.B, w.primes, rows=rows)
+    assert np.array_equal(ref[0][:, rows], wantA[:, rows]) and np.array_equal(ref[1][:, rows], wantB[:, rows])
