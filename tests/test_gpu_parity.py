@@ -254,3 +254,26 @@ def test_determinism_across_runs_tile_classes_and_forms():
     rows = [0, 255, 256, 1023]
     wantA, wantB = oracle.cp_mm(w.P, w.A, w.B, w.primes, rows=rows)
     assert np.array_equal(ref[0][:, rows], wantA[:, rows]) and np.array_equal(ref[1][:, rows], wantB[:, rows])
+
+
+@pytest.mark.parametrize("form", ["int8_crt", "int8", "fp64"])
+def test_plaintext_on_the_right_by_transposition(form):
+    """The paper's CP-MM returns an encryption of M U, the ciphertext parts times a plaintext on
+    the right (Section 2's problem statement; Eq LZoutput: (A U, B U)).  The library multiplies
+    the plaintext on the left, and (A U)^t = U^t A^t gives the right product from the transposed
+    operands; checked in full against the oracle's A U mod q, with a plaintext shared by both
+    parts and every prime."""
+    d1, d2, d3, L = 300, 500, 200, 2
+    primes = wl.ntt_primes(50, L, skip=3)
+    g = wl.rng(7500)
+    A = np.stack([wl.uniform_residues(g, (d1, d2), q) for q in primes])
+    B = np.stack([wl.uniform_residues(g, (d1, d2), q) for q in primes])
+    U = wl.plaintext_matrix(g, d2, d3)
+    tr = lambda X: np.ascontiguousarray(np.transpose(X, (0, 2, 1)))
+    PA, PB = hlb.cp_mm(_t(np.ascontiguousarray(U.T)), _t(tr(A)), _t(tr(B)), primes,
+                       p_absmax=int(np.abs(U).max()), form=form)
+    gotA, gotB = tr(_np(PA)), tr(_np(PB))
+    for i, q in enumerate(primes):
+        Uq = oracle.residues_of_signed(U, q)
+        assert np.array_equal(gotA[i], oracle.mod_pp_mm(q, A[i], Uq)), (i, "A U")
+        assert np.array_equal(gotB[i], oracle.mod_pp_mm(q, B[i], Uq)), (i, "B U")
