@@ -69,9 +69,11 @@ __device__ __forceinline__ uint32_t crt_y(int c, int p, int c16, float pinv) {
 // 2^14 of K, i.e. at most kCrtShortKB K blocks, of residues in [-128, 127]) and p >= 191 (every
 // modulus of the table):
 //  * x = c (1/p), with the conversion, the reciprocal and the product each rounded to
-//    nearest in single precision, is within 3 2^-24 |c / p| < 2^-2 of c / p;
-//  * so t = floor(x + 1/2) (one rounding conversion) is floor(c / p) or one more, and
-//    r = c - t p lies in [-p, p); |t| < 2^21, so one 24-bit multiply-add forms r exactly;
+//    nearest in single precision, is within 3 2^-24 |c / p| <= 48 / p < 0.26 of c / p;
+//  * so x + 1/2 (exact, or rounded to single precision: a change below 2^-3 at these
+//    magnitudes) lies within (c / p, c / p + 1), and t = floor(x + 1/2) (one rounding
+//    conversion) is floor(c / p) or one more; r = c - t p lies in [-p, p), and |t| < 2^21, so
+//    one 24-bit multiply-add forms r exactly;
 //  * one unsigned minimum maps [-p, 0) to [0, p), as in crt_y.
 constexpr int kCrtShortKB = 256;
 __device__ __forceinline__ uint32_t crt_y_short(int c, int negp, float pinv) {
