@@ -882,8 +882,11 @@ hlb_status run_products(const Plan &pl, const std::vector<LeftSpec> &lefts, cons
 
     void *wsP = nullptr, *wsX = nullptr;
     // FP64 plans with one plaintext limb run on prepared double planes (unless switched off)
-    const bool planes = pl.form == HLB_FORM_FP64 && pl.np == 1 && g_f64_planes.load() != 0 &&
-                        (pl.trunc ? pl.nx == 1 : (pl.nx == 3 || pl.nx == 4));
+    bool planes = pl.form == HLB_FORM_FP64 && pl.np == 1 && g_f64_planes.load() != 0 &&
+                  (pl.trunc ? pl.nx == 1 : (pl.nx == 3 || pl.nx == 4));
+    // the plane tiles address their K panels with 32-bit byte offsets: a deeper K stays on
+    // the register-staged kernel
+    if (planes && kblocks * f64_plane_bytes_x(pl.nx, 1, 1) > (int64_t)UINT32_MAX) planes = false;
     int64_t p_tile = (int64_t)pl.np * pl.bm * kBK8, x_tile = (int64_t)pl.nx * pl.bn * kBK8;
     if (planes) {
         p_tile = f64_plane_bytes_p(1, 1);

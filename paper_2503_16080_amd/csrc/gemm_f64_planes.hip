@@ -138,10 +138,14 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f64_planes_kernel(const Gemm
                 for (int i = 0; i < 4; ++i) part[a][b][i] = 0;
     }
 
+    // the buffer form of the direct-to-LDS load: the compiler counts it in vmcnt only, so the
+    // MFMAs wait for just the fragment reads they use (the host keeps KB X_BYTES below 2^32)
+    const __amdgpu_buffer_rsrc_t rsP = lds_src_rsrc(gP), rsX = lds_src_rsrc(gX);
     auto gload = [&](int kb, int buf) {
         int8_t *dst = lds + buf * T::STAGE;
-        copy_to_lds<kThreads, T::P_CHUNKS>(gP + (int64_t)kb * T::P_BYTES, dst, tid, wave_u);
-        copy_to_lds<kThreads, T::X_CHUNKS>(gX + (int64_t)kb * T::X_BYTES, dst + T::P_BYTES, tid, wave_u);
+        copy_to_lds_buf<kThreads, T::P_CHUNKS>(rsP, (uint32_t)kb * (uint32_t)T::P_BYTES, dst, tid, wave_u);
+        copy_to_lds_buf<kThreads, T::X_CHUNKS>(rsX, (uint32_t)kb * (uint32_t)T::X_BYTES, dst + T::P_BYTES, tid,
+                                               wave_u);
     };
     const int loads_per_stage = loads_of_wave<kThreads, T::P_CHUNKS>(wave_u) +
                                 loads_of_wave<kThreads, T::X_CHUNKS>(wave_u);
@@ -211,6 +215,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f64_planes_kernel(const Gemm
     wait_vmcnt(outstanding(0, T::NBUF - 1));
     stage_barrier();
     Frags f0, f1;
+    settle_scalar_loads();
     read_frags(f0, 0, 0);
 #pragma unroll 1
     for (int kb = 0; kb < KB; ++kb) {
