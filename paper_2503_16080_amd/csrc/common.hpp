@@ -92,27 +92,7 @@ __device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) {
 // LDS pipelines fed by direct-to-LDS global loads
 // ---------------------------------------------------------------------------------------
 
-// Copies CHUNKS 16-byte chunks from global memory to LDS with the gfx950 direct-to-LDS
-// load: lane l of a wave writes its 16 bytes at (wave-uniform LDS base) + 16 l, so the
-// linear chunk order of the tile-major workspace arrives unchanged and no staging
-// registers are used.  Chunks are dealt to waves in runs of 64.
-template <int THREADS, int CHUNKS>
-__device__ __forceinline__ void copy_to_lds(const int8_t *src, int8_t *dst, int tid, int wave_u) {
-#pragma unroll
-    for (int i = 0; i < (CHUNKS + THREADS - 1) / THREADS; ++i) {
-        const int base = i * THREADS + wave_u * 64;  // wave-uniform
-        if (CHUNKS % THREADS == 0 || base < CHUNKS)
-            __builtin_amdgcn_global_load_lds(
-                (const __attribute__((address_space(1))) void *)(src + (i * THREADS + tid) * 16),
-                (__attribute__((address_space(3))) void *)(dst + base * 16), 16, 0, 0);
-    }
-}
-
-// The same copy with the buffer form of the direct-to-LDS load (MUBUF ... lds): the source
-// is `rsrc` + src_off, byte offsets below 2^32.  The compiler counts these loads in vmcnt only,
-// so LDS fragment reads after them can wait for just the reads they need.  src_off is
-// wave-uniform and goes in the scalar offset; the per-lane offset is the same for every
-// stage and block, so one register serves all loads.
+// A buffer resource over a wave-uniform base, for the copies below.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t lds_src_rsrc(const int8_t *base) {
     // the base is wave-uniform; say so, so that the descriptor lives in scalar registers
     const uint64_t p = (uint64_t)(uintptr_t)base;
@@ -121,6 +101,15 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t lds_src_rsrc(const int8_t *bas
     return __builtin_amdgcn_make_buffer_rsrc((void *)(uintptr_t)(((uint64_t)hi << 32) | lo), 0, 0xffffffff,
                                              0x00020000);
 }
+// Copies CHUNKS 16-byte chunks from global memory to LDS with the buffer form of the gfx950
+// direct-to-LDS load (MUBUF ... lds): lane l of a wave writes its 16 bytes at (wave-uniform LDS
+// base) + 16 l, so the linear chunk order of the tile-major workspace arrives unchanged and no
+// staging registers are used; chunks are dealt to waves in runs of 64.  The source is `rsrc`
+// + src_off, byte offsets below 2^32.  The compiler counts these loads in vmcnt only (the
+// global form also counts as an LDS event, which makes every LDS read wait for all of them),
+// so LDS fragment reads after them can wait for just the reads they need.  src_off is
+// wave-uniform and goes in the scalar offset; the per-lane offset is the same for every stage
+// and block, so one register serves all loads.
 template <int THREADS, int CHUNKS>
 __device__ __forceinline__ void copy_to_lds_buf(__amdgpu_buffer_rsrc_t rsrc, uint32_t src_off, int8_t *dst, int tid,
                                                 int wave_u) {
