@@ -277,8 +277,12 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(w, target_s=15.0):
-    """The oracle timed on a bounded row sample of the same CP-MM (all primes, both parts)."""
+def cpu_baseline(w, gpu_out=None, target_s=15.0):
+    """The oracle timed on a bounded row sample of the same CP-MM (all primes, both parts).
+    With the GPU's output (PA, PB as host uint64 arrays) given, the sampled rows are compared
+    with it after the timing: `rows_equal_to_gpu` is whether every one matches."""
+    import numpy as np
+
     import oracle
     m, k, nA, nB, L = w.m, w.k, w.nA, w.nB, len(w.primes)
     per_row = L * k * (nA + nB)
@@ -288,12 +292,16 @@ def cpu_baseline(w, target_s=15.0):
     rows = int(max(1, min(m, target_s / max(t1, 1e-3))))
     sample = list(range(0, m, max(1, m // rows)))[:rows]
     t0 = time.perf_counter()
-    oracle.cp_mm(w.P, w.A, w.B, w.primes, rows=sample)
+    oA, oB = oracle.cp_mm(w.P, w.A, w.B, w.primes, rows=sample)
     dt = time.perf_counter() - t0
-    return {"value": len(sample) * per_row / dt, "unit": "mod-q MAC/s",
-            "cores": oracle.num_threads(), "cpu_model": cpu_model(), "kind": "oracle",
-            "sample": f"{len(sample)} of {m} output rows of the CP-MM (all {L} primes, a- and "
-                      f"b-parts), {dt:.1f} s; rate scales linearly with rows"}
+    res = {"value": len(sample) * per_row / dt, "unit": "mod-q MAC/s",
+           "cores": oracle.num_threads(), "cpu_model": cpu_model(), "kind": "oracle",
+           "sample": f"{len(sample)} of {m} output rows of the CP-MM (all {L} primes, a- and "
+                     f"b-parts), {dt:.1f} s; rate scales linearly with rows"}
+    if gpu_out is not None:
+        res["rows_equal_to_gpu"] = bool(np.array_equal(oA[:, sample], gpu_out[0][:, sample])
+                                        and np.array_equal(oB[:, sample], gpu_out[1][:, sample]))
+    return res
 
 
 def _roofline(kernel, launches, ms, ops_per_step, steps, d, L, peak, unit, op, bound="mfma"):
@@ -503,11 +511,13 @@ def config1_leg(steps, warmup, cpu=True):
     if cpu:
         import oracle
         t0 = time.perf_counter()
-        oracle.mod_pp_mm(q, P, X)
+        want = oracle.mod_pp_mm(q, P, X)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": macs / dt, "unit": "mod-q MAC/s", "cores": oracle.num_threads(),
                                "cpu_model": cpu_model(), "kind": "oracle",
                                "sample": f"the whole {n}^3 product, {dt:.3f} s"}
+        torch.cuda.synchronize()
+        out["bit_exact"] = {"oracle_equal": bool(np.array_equal(want, C.cpu().numpy().view(np.uint64)))}
     del Pd, Xd, C
     torch.cuda.empty_cache()
     return out
@@ -766,6 +776,10 @@ def main():
         "roofline": roofline("crt_gemm", kc["crt_gemm"][0], kc["crt_gemm"][1], c_ops, args.steps),
         "kernels_ms": {n: v[1] for n, v in kc.items()},
     }
+    # The headline form's output of its last timed step: every other form must reproduce it
+    # byte for byte, and the CPU baseline's oracle rows are compared with it.
+    ref_PA, ref_PB = PA.clone(), PB.clone()
+    identical = {}
 
     # The digit INT8 form (Strategy 1: 3 x 7 digit products per mod-q MAC)
     if not args.no_digit:
@@ -777,6 +791,7 @@ def main():
             "digits": [dplan["p_limbs"], dplan["x_limbs"]],
             "roofline": roofline("gemm_i8", kd["gemm_i8"][0], kd["gemm_i8"][1], d_ops, args.steps),
             "kernels_ms": {n: v[1] for n, v in kd.items()}}
+        identical["int8"] = bool(torch.equal(PA, ref_PA) and torch.equal(PB, ref_PB))
 
     if not args.no_fp64:
         fp_steps = max(2, args.steps // 3)
@@ -788,6 +803,7 @@ def main():
         hlb.set_option(hlb.OPT_PROFILE, 0)
         n_f, ms_f = hlb.profile_read("gemm_f64")
         hlb.profile_reset()
+        identical["fp64"] = bool(torch.equal(PA, ref_PA) and torch.equal(PB, ref_PB))
         fplan = hlb.plan(1, d, max(primes), p_absmax, "fp64")
         f_ops = 2.0 * fplan["p_limbs"] * fplan["x_limbs"] * macs
         f_tf = f_ops / (ms_f / max(n_f, 1) * 1e-3) / 1e12
@@ -802,6 +818,11 @@ def main():
         if "int8_digit_form" in out:
             out["slowdown_vs_fp64_gemm"]["int8_digit_form"] = s_dig / s_dgemm
 
+    out["bit_exact"] = {"forms_identical_to_int8_crt": identical}
+    ref_host = None
+    if w is not None:
+        ref_host = (ref_PA.cpu().numpy().view(np.uint64), ref_PB.cpu().numpy().view(np.uint64))
+    del ref_PA, ref_PB
     if not args.no_extra_configs:
         del P, A, B, PA, PB
         torch.cuda.empty_cache()
@@ -812,7 +833,8 @@ def main():
     if d == 8192:
         out["paper_figures"] = PAPER_FIGURES
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, ref_host)
+        out["bit_exact"]["oracle_rows_equal"] = out["cpu_baseline"]["rows_equal_to_gpu"]
 
     print(json.dumps(out), flush=True)
 

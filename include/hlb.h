@@ -304,6 +304,8 @@ typedef enum {
  *   HLB_FORM=auto|fp64|int8|int8_crt  the form of every call that passes HLB_FORM_AUTO
  *                                      (hlb_plan included); explicit forms are kept.
  *   HLB_VALIDATE=1                     starts HLB_OPT_VALIDATE on.
+ *   HLB_WS_CAP=bytes                   starts HLB_OPT_WS_CAP at that many bytes (a positive
+ *                                      decimal integer; anything else leaves no cap).
  *   HLB_TUNE_CACHE=path                tuning table loaded before the first lookup
  *                                      (hlb_tune_load's format).
  */

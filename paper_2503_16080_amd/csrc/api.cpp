@@ -35,7 +35,8 @@ static std::atomic<int> g_crt_wide{-1};  // -1: the tuned class per shape
 static std::atomic<int64_t> g_ws_cap{0};
 
 // Environment switches, read once per process: HLB_FORM names the form of calls that pass
-// HLB_FORM_AUTO (auto, fp64, int8 or int8_crt); HLB_VALIDATE=1 starts HLB_OPT_VALIDATE on.
+// HLB_FORM_AUTO (auto, fp64, int8 or int8_crt); HLB_VALIDATE=1 starts HLB_OPT_VALIDATE on;
+// HLB_WS_CAP=<bytes> starts HLB_OPT_WS_CAP at that value (ignored unless a positive integer).
 static std::once_flag g_env_once;
 static std::atomic<int> g_env_form{HLB_FORM_AUTO};
 static std::atomic<int> g_validate{0};
@@ -47,7 +48,16 @@ static void read_env() {
             else if (!std::strcmp(f, "int8_crt")) g_env_form.store(HLB_FORM_INT8_CRT);
         }
         if (const char *v = std::getenv("HLB_VALIDATE")) g_validate.store(*v && std::strcmp(v, "0") ? 1 : 0);
+        if (const char *c = std::getenv("HLB_WS_CAP")) {
+            char *end = nullptr;
+            const long long v = std::strtoll(c, &end, 10);
+            if (end != c && *end == '\0' && v > 0) g_ws_cap.store(v);
+        }
     });
+}
+static int64_t ws_cap() {
+    read_env();
+    return g_ws_cap.load();
 }
 int resolve_form(int form) {
     read_env();
@@ -452,7 +462,7 @@ static size_t ws_bucket(size_t bytes) {
 hlb_status ws_alloc(void **p, size_t bytes, hipStream_t s) {
     *p = nullptr;
     if (bytes == 0) return HLB_OK;
-    const int64_t cap = g_ws_cap.load();
+    const int64_t cap = ws_cap();
     if (cap > 0 && ws_bucket(bytes) > (size_t)cap) return HLB_ENOMEM;
     if (hipMallocAsync(p, ws_bucket(bytes), s) != hipSuccess) {
         (void)hipGetLastError();
@@ -517,7 +527,7 @@ ScratchScope::~ScratchScope() { t_scratch = prev_; }
 
 hlb_status WsLease::take(hipStream_t s, const size_t *bytes, void **ptrs, int n) {
     const ScratchScope *scr = t_scratch;
-    const int64_t cap = scr ? 0 : g_ws_cap.load();
+    const int64_t cap = scr ? 0 : ws_cap();
     size_t total = 0;
     for (int i = 0; i < n; ++i) {
         ptrs[i] = nullptr;
@@ -1380,6 +1390,7 @@ hlb_status hlb_set_option(int option, int64_t value) {
             return HLB_OK;
         case HLB_OPT_WS_CAP:
             if (value < 0) return HLB_EINVAL;
+            read_env();  // the option set here outlasts the environment's value
             g_ws_cap.store(value);
             return HLB_OK;
         case HLB_OPT_VALIDATE:

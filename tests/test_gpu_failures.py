@@ -96,3 +96,44 @@ def test_digit_form_refuses_k_beyond_32_bit_panel_offsets():
     k2 = 1 << 20
     got = hlb.mod_pp_mm(q, P[:, :k2].contiguous(), X[:k2].contiguous(), form="int8")
     assert int(_np(got)[0, 0]) == k2 % q
+
+
+def test_workspace_cap_from_environment():
+    """HLB_WS_CAP sets the workspace cap at process start (read once, so each setting runs in
+    a child process): a cap of 64 KiB refuses the call with HLB_ENOMEM and leaves the outputs
+    untouched; hlb_set_option then lifts it and the same call matches the oracle.  A value
+    that is not a positive integer sets no cap."""
+    import json
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import json, numpy as np, torch, oracle, workloads as wl, paper_2503_16080_amd as h\n"
+        "w = wl.cpmm_uniform(6101, 300, 260, 200, 50, 2)\n"
+        "t = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64) if a.dtype == np.uint64 "
+        "else np.ascontiguousarray(a)).to('cuda')\n"
+        "P, A, B = t(w.P), t(w.A), t(w.B)\n"
+        "PA = torch.full((2, 300, 200), -1, dtype=torch.int64, device='cuda'); PB = PA.clone()\n"
+        "res = []\n"
+        "try:\n"
+        "    h.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form='int8_crt', out=(PA, PB)); res.append(0)\n"
+        "except h.HlbError as e:\n"
+        "    res.append(e.status)\n"
+        "torch.cuda.synchronize(); res.append(bool((PA == -1).all()) and bool((PB == -1).all()))\n"
+        "h.set_option(h.OPT_WS_CAP, 0)\n"
+        "h.cp_mm(P, A, B, w.primes, p_absmax=w.p_absmax, form='int8_crt', out=(PA, PB))\n"
+        "wA, wB = oracle.cp_mm(w.P, w.A, w.B, w.primes)\n"
+        "res.append(bool(np.array_equal(PA.cpu().numpy().view(np.uint64), wA) and "
+        "np.array_equal(PB.cpu().numpy().view(np.uint64), wB)))\n"
+        "print(json.dumps(res))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    got = {}
+    for cap in ("65536", "12x"):
+        env = dict(os.environ, HLB_WS_CAP=cap)
+        print(f"child process with HLB_WS_CAP={cap}", flush=True)
+        r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                           timeout=180)
+        assert r.returncode == 0, r.stderr[-2000:]
+        got[cap] = json.loads(r.stdout.strip().splitlines()[-1])
+    assert got["65536"] == [ENOMEM, True, True]
+    assert got["12x"] == [0, False, True]
