@@ -185,78 +185,158 @@ __device__ __forceinline__ uint64_t reduce_u64(uint64_t x, uint64_t q, uint64_t 
 }
 
 // Thread: one lane's 16 entries of one 32 x 32 block (16 bytes of every plane, read as one
-// 16-byte load each); consecutive threads are consecutive lanes, so each row of a block is
-// written as 256 contiguous bytes.  S = sum_i y_i w_i < 16 * 2^8 * 2^52 is accumulated in
-// three 20-bit limbs of w_i (each limb sum stays below 2^32, 24-bit multiply-adds), and the
-// rounding t = round(sum_i y_i / p_i) needs only single precision: the fraction lies within
-// 1/4 of an integer, far beyond its rounding error.  (t M) mod q comes from a table in LDS.
-__device__ __forceinline__ void crt_tmq_table(const CrtCombineArgs &a, uint64_t *tmq) {
-    if (threadIdx.x <= (unsigned)a.D) tmq[threadIdx.x] = reduce_u64((uint64_t)threadIdx.x * a.Mq, a.q, a.barrett);
+// 16-byte load each, all issued before any arithmetic); consecutive threads are consecutive
+// lanes, so each row of a block is written as 256 contiguous bytes.  For each entry the
+// coefficients of four moduli are gathered into one word (a 4 x 4 byte transpose of four
+// planes' words), and byte dot products (v_dot4_u32_u8) form
+//   L_l = sum_i y_i w_i,l  (w_i,l: byte l of w_i = (M / p_i) mod q, l = 0..6; L_l < 2^20),
+//   T   = sum_i y_i c_i    (c_i = round(2^14 / p_i) <= 86).
+// S = sum_l L_l 2^(8 l) = sum_i y_i w_i <= 16 * 255 (q - 1), far below 2^64 - q.  The
+// rounding t = round(sum_i y_i / p_i) is floor(T / 2^14 + 1/2): the sum lies within 1/4 of
+// an integer (the moduli are chosen with M >= 4 |V|), and T / 2^14 differs from it by at most
+// sum_i y_i / 2^15 <= 16 * 255 / 2^15 < 1/8.  The output is x mod q for x = S + (-t M mod q),
+// with (-t M) mod q from a table in LDS; x < 4081 q, so its quotient has at most 12 bits.
+// The estimate floor(x / q - 1/2), formed in single precision (x, 1/q and the product each
+// within a few units of 2^-24 relatively: within 0.002 of x / q - 1/2 below 2^12), is
+// floor(x / q) or one less, and one conditional subtraction finishes.
+__device__ __forceinline__ uint64_t crt_reduce_small_quotient(uint32_t x_lo, uint32_t x_hi, uint64_t q, float qinv) {
+    const float xf = __builtin_fmaf((float)x_hi, 4294967296.0f, (float)x_lo);
+    const uint32_t qt = (uint32_t)__builtin_fmaxf(__builtin_fmaf(xf, qinv, -0.5f), 0.0f);
+    const uint64_t r = (((uint64_t)x_hi << 32) | x_lo) - (uint64_t)qt * q;
+    return r >= q ? r - q : r;
+}
+__device__ __forceinline__ void crt_negtm_table(const CrtCombineArgs &a, uint64_t *tab) {
+    if (threadIdx.x <= (unsigned)a.D) {
+        const uint64_t tm = reduce_u64((uint64_t)threadIdx.x * a.Mq, a.q, a.barrett);
+        tab[threadIdx.x] = tm == 0 ? 0 : a.q - tm;
+    }
     __syncthreads();
 }
 
-// Entries g of one output matrix (g = 64 * (32 x 32 block) + lane, g < 64 * blocks).
-__device__ __forceinline__ void crt_combine_lane(const CrtCombineArgs &a, const uint64_t *tmq, int64_t g,
-                                                 int64_t nbc_valid) {
-    const int lane = (int)(g & 63);
-    const int64_t b = g >> 6, br = b / nbc_valid, bc = b - br * nbc_valid;
+// c_4g .. c_4g+3 (c_i = round(2^14 / p_i)) as the bytes of one word.
+constexpr uint32_t crt_round_word(int g) {
+    uint32_t v = 0;
+    for (int j = 0; j < 4; ++j) {
+        const int p = kCrtModuli[4 * g + j];
+        v |= (uint32_t)((32768 + p) / (2 * p)) << (8 * j);
+    }
+    return v;
+}
+
+// Rows a, b, c, d of a 4 x 4 byte matrix (one word each) to its columns: o[j] holds byte j of
+// a, b, c and d, in that order.
+__device__ __forceinline__ void crt_transpose4(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t (&o)[4]) {
+    const uint32_t t0 = __builtin_amdgcn_perm(b, a, 0x05010400u);  // a0 b0 a1 b1
+    const uint32_t t1 = __builtin_amdgcn_perm(b, a, 0x07030602u);  // a2 b2 a3 b3
+    const uint32_t t2 = __builtin_amdgcn_perm(d, c, 0x05010400u);  // c0 d0 c1 d1
+    const uint32_t t3 = __builtin_amdgcn_perm(d, c, 0x07030602u);  // c2 d2 c3 d3
+    o[0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
+    o[1] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+    o[2] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+    o[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
+}
+
+// The 16 entries of one lane of block (br, bc), for G groups of four moduli (4 G >= D; the
+// planes past D read as zero).  CHECK: some rows of the block lie past m.
+template <int G, bool CHECK>
+__device__ __forceinline__ void crt_combine_entries(const CrtCombineArgs &a, const uint64_t *tab, int64_t br,
+                                                    int64_t bc, int lane) {
     const uint8_t *y = a.Y + ((br * a.nbc + bc) * 64 + lane) * 16;
-    uint32_t s0[16], s1[16], s2[16];
-    float f[16];
+    uint4 v[4 * G];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        s0[e] = s1[e] = s2[e] = 0u;
-        f[e] = 0.f;
+    for (int i = 0; i < 4 * G; ++i) {
+        if (i < 4 * (G - 1) || i < a.D) v[i] = *(const uint4 *)(y + (int64_t)i * a.plane);
+        else v[i] = uint4{0u, 0u, 0u, 0u};
     }
-#pragma unroll 2
-    for (int i = 0; i < a.D; ++i) {
-        const uint4 v = *(const uint4 *)(y + (int64_t)i * a.plane);
-        const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
-        const uint64_t w = a.w[i];
-        const uint32_t w0 = (uint32_t)w & 0xfffffu, w1 = (uint32_t)(w >> 20) & 0xfffffu, w2 = (uint32_t)(w >> 40);
-        const float pi = a.pinv[i];
+    // byte l of w_4g .. w_4g+3 as one word (uniform; w_i = 0 past D)
+    uint32_t wl[7][G];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const uint32_t byte = (vw[e >> 2] >> (8 * (e & 3))) & 0xffu;
-            s0[e] += __umul24(byte, w0);
-            s1[e] += __umul24(byte, w1);
-            s2[e] += __umul24(byte, w2);
-            f[e] = __builtin_fmaf((float)byte, pi, f[e]);
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int l = 0; l < 7; ++l) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) word |= (uint32_t)((a.w[4 * g + j] >> (8 * l)) & 0xffu) << (8 * j);
+            wl[l][g] = word;
         }
-    }
-    const int64_t col = bc * 32 + (lane & 31);
-    if (col >= a.n) return;
+    const float qinv = 1.0f / (float)a.q;
+    const int64_t row0 = br * 32 + 4 * (lane >> 5);
+    uint64_t *out = a.C + row0 * a.ldc + bc * 32 + (lane & 31);  // advanced row by row below
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int64_t row = br * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        if (row >= a.m) continue;
-        const uint64_t sum = ((uint64_t)s2[e] << 40) + ((uint64_t)s1[e] << 20) + s0[e];
-        const uint64_t sr = reduce_u64(sum, a.q, a.barrett);
-        const uint64_t tm = tmq[(int)__builtin_floorf(f[e] + 0.5f)];
-        // streaming store: the outputs are not read again here
-        __builtin_nontemporal_store(sr >= tm ? sr - tm : sr + a.q - tm, &a.C[row * a.ldc + col]);
+    for (int k = 0; k < 4; ++k) {  // word k of each plane: entries 4 k .. 4 k + 3
+        uint32_t yt[4][G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t wa[4] = {v[4 * g].x, v[4 * g].y, v[4 * g].z, v[4 * g].w};
+            const uint32_t wb[4] = {v[4 * g + 1].x, v[4 * g + 1].y, v[4 * g + 1].z, v[4 * g + 1].w};
+            const uint32_t wc[4] = {v[4 * g + 2].x, v[4 * g + 2].y, v[4 * g + 2].z, v[4 * g + 2].w};
+            const uint32_t wd[4] = {v[4 * g + 3].x, v[4 * g + 3].y, v[4 * g + 3].z, v[4 * g + 3].w};
+            uint32_t o[4];
+            crt_transpose4(wa[k], wb[k], wc[k], wd[k], o);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) yt[b][g] = o[b];
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {  // entry 4 k + b: row 8 k + b of this lane's half-block
+            uint32_t L[7], T = 0;
+#pragma unroll
+            for (int l = 0; l < 7; ++l) L[l] = 0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+#pragma unroll
+                for (int l = 0; l < 7; ++l) L[l] = __builtin_amdgcn_udot4(yt[b][g], wl[l][g], L[l], false);
+                T = __builtin_amdgcn_udot4(yt[b][g], crt_round_word(g), T, false);
+            }
+            // x = S + (-t M mod q) as two words: S = lo + mid 2^16 + hi 2^32 with lo, mid < 2^29
+            // and hi < 2^32 (S < 2^64); no carry leaves the high word (x < 2^64)
+            const uint32_t lo = L[0] + (L[1] << 8), mid = L[2] + (L[3] << 8), hi = L[4] + (L[5] << 8) + (L[6] << 16);
+            const uint64_t e = tab[(T + 8192u) >> 14];
+            uint32_t c0, c1;
+            const uint32_t s_lo = __builtin_addc(lo, mid << 16, 0u, &c0);
+            const uint32_t x_lo = __builtin_addc(s_lo, (uint32_t)e, 0u, &c1);
+            const uint32_t x_hi = (mid >> 16) + hi + (uint32_t)(e >> 32) + c0 + c1;
+            const uint64_t r = crt_reduce_small_quotient(x_lo, x_hi, a.q, qinv);
+            if (!CHECK || row0 + 8 * k + b < a.m) __builtin_nontemporal_store(r, out);  // streaming store
+            out += b < 3 ? a.ldc : 5 * a.ldc;
+        }
     }
 }
 
-// Many output matrices in one launch: each workgroup serves kThreads entry groups of the job
-// that owns it.
-__device__ __forceinline__ void crt_combine_job(const CrtCombineJob &j, uint64_t *tmq) {
-    crt_tmq_table(j.a, tmq);
-    const int64_t nbc_valid = (j.a.n + 31) >> 5;
-    const int64_t total = ((j.a.m + 31) >> 5) * nbc_valid * 64;
-    const int64_t g = ((int64_t)blockIdx.x - j.wg_start) * kThreads + threadIdx.x;
-    if (g < total) crt_combine_lane(j.a, tmq, g, nbc_valid);
+// Many output matrices in one launch: each workgroup serves kThreads / 64 blocks of the job
+// that owns it, one per wave (the block index is uniform over a wave).
+__device__ __forceinline__ void crt_combine_job(const CrtCombineJob &j, uint64_t *tab) {
+    const CrtCombineArgs &a = j.a;
+    crt_negtm_table(a, tab);
+    const int64_t nbc_valid = (a.n + 31) >> 5;
+    const int64_t blocks = ((a.m + 31) >> 5) * nbc_valid;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t blk = ((int64_t)blockIdx.x - j.wg_start) * (kThreads / 64) + wave;
+    if (blk >= blocks) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t br = blk / nbc_valid, bc = blk - br * nbc_valid;
+    if (bc * 32 + (lane & 31) >= a.n) return;
+    const bool full = br * 32 + 32 <= a.m;
+    if (a.D <= 8) {
+        if (full) crt_combine_entries<2, false>(a, tab, br, bc, lane);
+        else crt_combine_entries<2, true>(a, tab, br, bc, lane);
+    } else if (a.D <= 12) {
+        if (full) crt_combine_entries<3, false>(a, tab, br, bc, lane);
+        else crt_combine_entries<3, true>(a, tab, br, bc, lane);
+    } else {
+        if (full) crt_combine_entries<4, false>(a, tab, br, bc, lane);
+        else crt_combine_entries<4, true>(a, tab, br, bc, lane);
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void crt_combine_batch(const CrtCombineJob *__restrict__ jobs, int njobs) {
-    __shared__ uint64_t tmq[kCrtMaxModuli + 1];
-    crt_combine_job(jobs[crt_job_of(jobs, njobs, blockIdx.x)], tmq);
+    __shared__ uint64_t tab[kCrtMaxModuli + 1];
+    crt_combine_job(jobs[crt_job_of(jobs, njobs, blockIdx.x)], tab);
 }
 
 // The same with the job table in the kernel arguments (the outputs of one call).
 __global__ __launch_bounds__(kThreads) void crt_combine_tab(const CrtCombineTable t) {
-    __shared__ uint64_t tmq[kCrtMaxModuli + 1];
-    crt_combine_job(t.job[crt_tab_job(t.start, (int)blockIdx.x)], tmq);
+    __shared__ uint64_t tab[kCrtMaxModuli + 1];
+    crt_combine_job(t.job[crt_tab_job(t.start, (int)blockIdx.x)], tab);
 }
 
 // ---------------------------------------------------------------------------------------
