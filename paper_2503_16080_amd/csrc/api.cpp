@@ -832,10 +832,7 @@ static hlb_status run_products_crt(const Plan &pl, const std::vector<LeftSpec> &
         c.barrett = (uint64_t)((~(unsigned __int128)0 >> 64) / c.q);
         c.Mq = (uint64_t)(M % c.q);
         c.D = D;
-        for (int jj = 0; jj < D; ++jj) {
-            c.w[jj] = (uint64_t)((M / (unsigned)kCrtModuli[jj]) % c.q);
-            c.pinv[jj] = 1.0f / (float)kCrtModuli[jj];
-        }
+        for (int jj = 0; jj < D; ++jj) c.w[jj] = (uint64_t)((M / (unsigned)kCrtModuli[jj]) % c.q);
         return true;
     };
 

@@ -399,10 +399,7 @@ hlb_status build_crt_layout(const hlb_cpmm_problem *probs, int count, const uint
                 c.barrett = (uint64_t)((~(unsigned __int128)0 >> 64) / c.q);
                 c.Mq = (uint64_t)(M % c.q);
                 c.D = D;
-                for (int j = 0; j < D; ++j) {
-                    c.w[j] = (uint64_t)((M / (unsigned)kCrtModuli[j]) % c.q);
-                    c.pinv[j] = 1.0f / (float)kCrtModuli[j];
-                }
+                for (int j = 0; j < D; ++j) c.w[j] = (uint64_t)((M / (unsigned)kCrtModuli[j]) % c.q);
                 lay.cjobs.push_back(cj);
                 lay.combine_wgs += crt_combine_wgs(p.m, n);
                 y_off += (size_t)(D * sg.plane);

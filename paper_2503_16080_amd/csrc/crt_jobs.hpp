@@ -59,8 +59,7 @@ struct CrtCombineArgs {
     uint64_t q;
     uint64_t barrett;    // floor(2^64 / q)
     uint64_t Mq;         // M mod q
-    uint64_t w[kCrtMaxModuli];
-    float pinv[kCrtMaxModuli];  // 1 / p_i
+    uint64_t w[kCrtMaxModuli];  // (M / p_i) mod q; zero past D
     int32_t D, pad;
 };
 
