@@ -151,14 +151,20 @@ __device__ __forceinline__ int crt_job_of(const J *__restrict__ jobs, int njobs,
 
 // Many operands in one launch (left operands are scaled by `scale`, right operands centred
 // modulo their job's modulus): workgroup w serves the job that owns it.
+// Consecutive workgroups take consecutive k blocks of a left operand's row tile (each row's
+// bytes are read in order) and consecutive column tiles of a right operand at one k block (each
+// row of the operand is read in order across them).
 template <int D>
 __device__ __forceinline__ void crt_split_job(const CrtSplitJob &j, int64_t w, const CrtScale &scale) {
     const int64_t local = w - j.wg_start;
-    const int tile = (int)(local / j.kblocks), kb = (int)(local % j.kblocks);
-    if (j.rows_side)
+    if (j.rows_side) {
+        const int tile = (int)(local / j.kblocks), kb = (int)(local % j.kblocks);
         crt_split_rows_tile<D>((const int64_t *)j.src, j.ld, j.extent, j.k, j.kblocks, tile, kb, j.qc, scale, j.out);
-    else
+    } else {
+        const int64_t tiles = (j.extent + kCrtR - 1) / kCrtR;
+        const int tile = (int)(local % tiles), kb = (int)(local / tiles);
         crt_split_cols_tile<D>((const uint64_t *)j.src, j.ld, j.k, j.extent, j.kblocks, tile, kb, j.qc, j.out);
+    }
 }
 
 template <int D>
