@@ -211,6 +211,8 @@ __device__ __forceinline__ uint64_t crt_reduce_small_quotient(uint32_t x_lo, uin
     const uint64_t r = (((uint64_t)x_hi << 32) | x_lo) - (uint64_t)qt * q;
     return r >= q ? r - q : r;
 }
+
+// The table (-t M) mod q for t = 0 .. D (t <= D since sum_i y_i / p_i < D), in LDS.
 __device__ __forceinline__ void crt_negtm_table(const CrtCombineArgs &a, uint64_t *tab) {
     if (threadIdx.x <= (unsigned)a.D) {
         const uint64_t tm = reduce_u64((uint64_t)threadIdx.x * a.Mq, a.q, a.barrett);
